@@ -1,0 +1,134 @@
+/*
+ * fem.h -- C ABI of libfem: element stiffness-matrix and load-vector integration for
+ * tensor-product Lagrange hexahedra of degree p = 1..7 on one AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the element-level numerical integration of Banas, Plaszewski and Maciol,
+ * "Numerical integration on GPUs for higher order finite elements": Algorithm 1 and
+ * Algorithm 2 of section 2 (loop over quadrature points; per point the Jacobian, its
+ * determinant and inverse, the physical derivatives psi, the point coefficients c^Q, then an
+ * update of every entry of A^e), with the element entry of eq. (sum_int) of section 5.1,
+ * specialised to one scalar unknown and the convection-diffusion-reaction form
+ *
+ *   A[i][j] = sum_q w_q detJ_q [ sum_kl K_kl d_k phi_i d_l phi_j
+ *                                + phi_i sum_k b_k d_k phi_j + c phi_i phi_j ]
+ *   b[i]    = sum_q w_q detJ_q f phi_i
+ *
+ * Element conventions. Reference cube [-1,1]^3. Vertex v = v1 + 2 v2 + 4 v3 of an element sits
+ * at xi = (2v1-1, 2v2-1, 2v3-1); the geometry is the trilinear map of the 8 vertices. Shape
+ * functions are tensor products of the 1-D Lagrange polynomials on the p+1 Gauss-Lobatto-
+ * Legendre nodes, node i = a + n b + n^2 c with n = p+1 and Ns = n^3. The quadrature is the
+ * (p+1)^3-point Gauss-Legendre rule. J[a][b] = dx_a/dxi_b; physical gradients are J^{-T}
+ * times reference gradients. Row i of A is the test function, column j the trial function.
+ *
+ * Memory. Every array pointer is a DEVICE pointer owned by the caller, unless marked HOST.
+ * Nothing is allocated or freed by fem_integrate; fem_init allocates the library's constant
+ * tables once per process. Calls enqueue work on `stream` (a hipStream_t; NULL = the null
+ * stream) and return without synchronising.
+ *
+ * Errors. Every function returns a fem_status. Argument errors are detected on the host before
+ * anything is enqueued; HIP launch errors map to FEM_EHIP. Data errors (detJ <= 0 at some
+ * quadrature point, non-finite values) are counted asynchronously into coeffs->status; such
+ * elements are still integrated, with the signed detJ.
+ */
+#ifndef FEM_H
+#define FEM_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FEM_ABI_VERSION 1
+
+typedef enum {
+    FEM_OK = 0,
+    FEM_EINVAL = -1,     /* a null pointer, a negative count or an unknown enum value */
+    FEM_EDEGREE = -2,    /* p outside 1..7 (or p == 0 without a degree array) */
+    FEM_ENOTINIT = -3,   /* fem_init has not succeeded in this process */
+    FEM_ENOMEM = -4,     /* fem_init could not allocate its tables */
+    FEM_EHIP = -5,       /* a HIP runtime call or kernel launch failed */
+    FEM_ECONFIG = -6,    /* no compiled kernel configuration for the request */
+    FEM_EWORKSPACE = -7  /* workspace missing or smaller than fem_workspace_bytes() */
+} fem_status;
+
+/* Arithmetic of the contraction A = B^T blockdiag(D_q) B. The Jacobian, its determinant and
+ * inverse are computed in FP64 on every path; the load vector is accumulated in FP64.
+ *   FEM_FP64        FP64 MFMA, FP64 output
+ *   FEM_FP32        FP32 MFMA, FP32 output
+ *   FEM_BF16        one BF16 MFMA product per term, FP32 accumulation, FP32 output
+ *   FEM_SPLIT_BF16  x = hi + lo in BF16 on both operands; hi*hi + hi*lo + lo*hi, FP32 acc.
+ *   FEM_SPLIT_FP16  the same three products in FP16 with exact power-of-two scaling
+ */
+typedef enum {
+    FEM_FP64 = 0,
+    FEM_FP32 = 1,
+    FEM_BF16 = 2,
+    FEM_SPLIT_BF16 = 3,
+    FEM_SPLIT_FP16 = 4
+} fem_precision;
+
+/* How the coefficients are given (section 2: c per element, or c^Q per quadrature point).
+ *   FEM_COEF_ELEMENT  elem[e][14] = K (3x3 row-major), b (3), c, f; constant on the element
+ *   FEM_COEF_FIELD    elem[e][10] = Q (3x3 row-major), f; plus `field`, 7 fields x 5 modes x
+ *                     (a, k1, k2, k3, theta) = 175 doubles. Field s at x is
+ *                     g_s(x) = sum_m a_sm sin(2 pi (k_sm . x) + theta_sm) and at each
+ *                     quadrature point x_q: K = Q diag(10^g0, 10^g1, 10^g2) Q^T,
+ *                     b = (g3, g4, g5), c = (1 + g6) / 2; f stays per element. */
+typedef enum { FEM_COEF_ELEMENT = 0, FEM_COEF_FIELD = 1 } fem_coef_mode;
+
+/* Per-call description of the coefficients and of optional mixed-degree data. HOST struct,
+ * read during the call only; the pointers inside are DEVICE pointers. */
+typedef struct fem_coeffs {
+    int32_t precision;       /* fem_precision; FEM_FP64 -> out_A/out_b are double, else float */
+    int32_t mode;            /* fem_coef_mode */
+    const double *elem;      /* [nel][14] or [nel][10] FP64 records, see fem_coef_mode */
+    const double *field;     /* [175] FP64, FIELD mode only, else ignored */
+    const int8_t *degree;    /* [nel] per-element degree 1..7 when p == 0, else ignored */
+    const int64_t *a_off;    /* [nel+1] element offsets (in entries) into out_A when p == 0 */
+    const int64_t *b_off;    /* [nel+1] element offsets into out_b when p == 0 */
+    int32_t *status;         /* [2] or NULL: atomically adds #elements with detJ <= 0 and
+                                #elements with a non-finite input or output */
+    void *workspace;         /* mixed degree only: fem_workspace_bytes(nel) bytes, 256-B aligned */
+    size_t workspace_bytes;
+} fem_coeffs;
+
+/* Make `device` current, build the FP64 reference tables for p = 1..7 (quadrature, 1-D
+ * Lagrange values and derivatives, the B^T operand tables in every precision) and upload them.
+ * Idempotent for the same device. Not thread-safe; call before any other function. */
+int fem_init(int device);
+
+/* Release the tables. Afterwards every call but fem_init returns FEM_ENOTINIT. */
+int fem_finalize(void);
+
+/* Integrate nel elements (Algorithm 2 of section 2 for each element, all elements in parallel:
+ * elements over workgroups and entries of A^e over threads, section 4).
+ *   nel    >= 0; nel == 0 returns FEM_OK and enqueues nothing
+ *   p      1..7 for a uniform degree; 0 selects the per-element degrees coeffs->degree, which
+ *          then also needs coeffs->a_off, coeffs->b_off (if out_b) and coeffs->workspace
+ *   geom   [nel][8][3] FP64 vertex coordinates
+ *   out_A  uniform p: [nel][Ns][Ns] row-major, unpadded; mixed: element e at a_off[e]
+ *   out_b  uniform p: [nel][Ns]; mixed: element e at b_off[e]; may be NULL
+ * Outputs are double for FEM_FP64 and float otherwise. */
+int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coeffs, void *out_A,
+                  void *out_b, void *stream);
+
+/* Bytes of device workspace that a mixed-degree fem_integrate over nel elements needs. */
+size_t fem_workspace_bytes(int64_t nel);
+
+/* Exclusive scans a_off[e] = sum_{e' < e} Ns(e')^2 and b_off[e] = sum_{e' < e} Ns(e') over a
+ * device degree array, nel + 1 entries each, computed on the device. `workspace` as for
+ * fem_integrate. Degrees outside 1..7 count as 0 entries and are rejected by fem_integrate. */
+int fem_mixed_offsets(int64_t nel, const int8_t *degree, int64_t *a_off, int64_t *b_off,
+                      void *workspace, size_t workspace_bytes, void *stream);
+
+/* Static text for a status code. Never NULL. */
+const char *fem_strerror(int status);
+
+/* FEM_ABI_VERSION of the loaded library. */
+int fem_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,329 @@
+/*
+ * fem_oracle.c -- FP64 CPU oracle for element integration (declarations and conventions in
+ * fem_oracle.h).
+ *
+ * TEST INFRASTRUCTURE: only the tests, the package's smoke check and the benchmark's
+ * CPU-baseline leg load this code. It is deliberately plain: one element at a time, loops in
+ * the order of Algorithm 2 (quadrature points outermost, section 2), no blocking, no fusion,
+ * no precomputed tables shared between elements, OpenMP over elements only (the CPU
+ * parallelisation the paper measures against, section 5.2).
+ */
+#include "fem_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define MAX_N 8 /* p <= 7 */
+#define MAX_NS (MAX_N * MAX_N * MAX_N)
+
+/* Legendre polynomial P_n(x) and P_{n-1}(x) by the three-term recurrence
+ * (k+1) P_{k+1} = (2k+1) x P_k - k P_{k-1}. */
+static void legendre_pair(int n, double x, double *pn, double *pnm1)
+{
+    double p0 = 1.0, p1 = x;
+    if (n == 0) {
+        *pn = 1.0;
+        *pnm1 = 0.0;
+        return;
+    }
+    for (int k = 1; k < n; ++k) {
+        double p2 = ((2.0 * k + 1.0) * x * p1 - k * p0) / (k + 1.0);
+        p0 = p1;
+        p1 = p2;
+    }
+    *pn = p1;
+    *pnm1 = p0;
+}
+
+/* Quadrature points and weights xi^Q, w^Q (section 2). The paper asks for a Gaussian rule; the
+ * reading used here is Gauss-Legendre with n = p+1 points per direction. Roots of P_n by Newton
+ * from x0 = cos(pi (k - 1/4) / (n + 1/2)); weight 2 / ((1 - x^2) P_n'(x)^2). */
+int oracle_gauss_legendre(int n, double *x, double *w)
+{
+    if (n < 1 || n > 64)
+        return -1;
+    for (int k = 1; k <= n; ++k) {
+        double r = cos(M_PI * (k - 0.25) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double pn, pnm1;
+            legendre_pair(n, r, &pn, &pnm1);
+            dp = n * (r * pn - pnm1) / (r * r - 1.0);
+            double dx = pn / dp;
+            r -= dx;
+            if (fabs(dx) < 1e-16)
+                break;
+        }
+        {
+            double pn, pnm1;
+            legendre_pair(n, r, &pn, &pnm1);
+            dp = n * (r * pn - pnm1) / (r * r - 1.0);
+        }
+        /* k = 1 gives the largest root: store descending from the top, i.e. ascending. */
+        x[n - k] = r;
+        w[n - k] = 2.0 / ((1.0 - r * r) * dp * dp);
+    }
+    return 0;
+}
+
+/* Gauss-Lobatto-Legendre nodes: -1, the p-1 roots of P_p', +1. Newton on P_p' with
+ * P_p'' = (2 x P_p' - p(p+1) P_p) / (1 - x^2), started from the Chebyshev-Gauss-Lobatto points. */
+int oracle_gll_nodes(int p, double *x)
+{
+    if (p < 1 || p > 63)
+        return -1;
+    x[0] = -1.0;
+    x[p] = 1.0;
+    for (int k = 1; k < p; ++k) {
+        double r = -cos(M_PI * k / p);
+        for (int it = 0; it < 100; ++it) {
+            double pn, pnm1;
+            legendre_pair(p, r, &pn, &pnm1);
+            double d1 = p * (r * pn - pnm1) / (r * r - 1.0);
+            double d2 = (2.0 * r * d1 - p * (p + 1.0) * pn) / (1.0 - r * r);
+            double dx = d1 / d2;
+            r -= dx;
+            if (fabs(dx) < 1e-16)
+                break;
+        }
+        x[k] = r;
+    }
+    return 0;
+}
+
+/* Lagrange polynomials l_a(x) = prod_{b != a} (x - x_b)/(x_a - x_b) and their derivatives
+ * l_a'(x) = sum_{m != a} 1/(x_a - x_m) prod_{b != a, m} (x - x_b)/(x_a - x_b). */
+void oracle_lagrange(int n, const double *nodes, double x, double *val, double *der)
+{
+    for (int a = 0; a < n; ++a) {
+        double v = 1.0;
+        for (int b = 0; b < n; ++b)
+            if (b != a)
+                v *= (x - nodes[b]) / (nodes[a] - nodes[b]);
+        val[a] = v;
+        double d = 0.0;
+        for (int m = 0; m < n; ++m) {
+            if (m == a)
+                continue;
+            double t = 1.0 / (nodes[a] - nodes[m]);
+            for (int b = 0; b < n; ++b)
+                if (b != a && b != m)
+                    t *= (x - nodes[b]) / (nodes[a] - nodes[b]);
+            d += t;
+        }
+        der[a] = d;
+    }
+}
+
+/* g_s(x) = sum_m a_sm sin(2 pi (k_sm . x) + theta_sm), s = 0..6, m = 0..4. */
+void oracle_field_eval(const double *field, const double *x, double *g)
+{
+    for (int s = 0; s < 7; ++s) {
+        double acc = 0.0;
+        for (int m = 0; m < 5; ++m) {
+            const double *md = field + (s * 5 + m) * 5;
+            double arg = 2.0 * M_PI * (md[1] * x[0] + md[2] * x[1] + md[3] * x[2]) + md[4];
+            acc += md[0] * sin(arg);
+        }
+        g[s] = acc;
+    }
+}
+
+/* The problem-dependent coefficients at one quadrature point (Algorithm 2, the step that forms
+ * c^Q[i_Q] from c). Out: K row-major 3x3, b, c, f. */
+static void point_coefficients(int mode, const double *rec, const double *field, const double *xq,
+                               double *K, double *bv, double *c, double *f)
+{
+    if (mode == ORACLE_COEF_ELEMENT) {
+        for (int t = 0; t < 9; ++t)
+            K[t] = rec[t];
+        for (int t = 0; t < 3; ++t)
+            bv[t] = rec[9 + t];
+        *c = rec[12];
+        *f = rec[13];
+        return;
+    }
+    double g[7];
+    oracle_field_eval(field, xq, g);
+    double lam[3] = {pow(10.0, g[0]), pow(10.0, g[1]), pow(10.0, g[2])};
+    const double *Q = rec;
+    for (int r = 0; r < 3; ++r)
+        for (int s = 0; s < 3; ++s) {
+            double acc = 0.0;
+            for (int t = 0; t < 3; ++t)
+                acc += Q[r * 3 + t] * lam[t] * Q[s * 3 + t];
+            K[r * 3 + s] = acc;
+        }
+    bv[0] = g[3];
+    bv[1] = g[4];
+    bv[2] = g[5];
+    *c = 0.5 * (1.0 + g[6]);
+    *f = rec[9];
+}
+
+/* One element, following Algorithm 2 of section 2: read coefficients and geometry, zero A^e,
+ * then for each quadrature point read the reference shape functions, compute the Jacobian, its
+ * determinant and inverse, the physical derivatives psi, the point coefficients, and update every
+ * (i, j) entry. Returns ORACLE_FLAG_* bits. */
+static int integrate_one(int p, const double *X, int mode, const double *rec, const double *field,
+                         double *A, double *bvec)
+{
+    const int n = p + 1;
+    const int ns = n * n * n;
+    double gx[MAX_N], gw[MAX_N], nodes[MAX_N];
+    double L[MAX_N][MAX_N], D[MAX_N][MAX_N]; /* [point][node] */
+    double phi[MAX_NS][4], psi[MAX_NS][4];
+    int flags = 0;
+
+    oracle_gauss_legendre(n, gx, gw);
+    oracle_gll_nodes(p, nodes);
+    for (int q = 0; q < n; ++q)
+        oracle_lagrange(n, nodes, gx[q], L[q], D[q]);
+
+    for (int t = 0; t < 24; ++t)
+        if (!isfinite(X[t]))
+            flags |= ORACLE_FLAG_NONFINITE;
+
+    memset(A, 0, sizeof(double) * (size_t)ns * ns);
+    if (bvec)
+        memset(bvec, 0, sizeof(double) * (size_t)ns);
+
+    for (int q3 = 0; q3 < n; ++q3)
+        for (int q2 = 0; q2 < n; ++q2)
+            for (int q1 = 0; q1 < n; ++q1) {
+                const double xi[3] = {gx[q1], gx[q2], gx[q3]};
+                const double wq = gw[q1] * gw[q2] * gw[q3];
+
+                /* reference values and derivatives phi^Q[i_Q] */
+                for (int c = 0; c < n; ++c)
+                    for (int b = 0; b < n; ++b)
+                        for (int a = 0; a < n; ++a) {
+                            int i = a + n * b + n * n * c;
+                            phi[i][0] = L[q1][a] * L[q2][b] * L[q3][c];
+                            phi[i][1] = D[q1][a] * L[q2][b] * L[q3][c];
+                            phi[i][2] = L[q1][a] * D[q2][b] * L[q3][c];
+                            phi[i][3] = L[q1][a] * L[q2][b] * D[q3][c];
+                        }
+
+                /* Jacobian of the trilinear map, J[a][b] = dx_a / dxi_b */
+                double J[3][3] = {{0}}, xq[3] = {0, 0, 0};
+                for (int v = 0; v < 8; ++v) {
+                    const double s1 = (v & 1) ? 1.0 : -1.0;
+                    const double s2 = (v & 2) ? 1.0 : -1.0;
+                    const double s3 = (v & 4) ? 1.0 : -1.0;
+                    const double f1 = 1.0 + s1 * xi[0], f2 = 1.0 + s2 * xi[1], f3 = 1.0 + s3 * xi[2];
+                    const double Nv = f1 * f2 * f3 / 8.0;
+                    const double dN[3] = {s1 * f2 * f3 / 8.0, f1 * s2 * f3 / 8.0, f1 * f2 * s3 / 8.0};
+                    for (int a = 0; a < 3; ++a) {
+                        xq[a] += X[v * 3 + a] * Nv;
+                        for (int b = 0; b < 3; ++b)
+                            J[a][b] += X[v * 3 + a] * dN[b];
+                    }
+                }
+                const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                   J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                   J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+                if (!(det > 0.0))
+                    flags |= ORACLE_FLAG_DETJ;
+                double Ji[3][3]; /* inverse = adjugate / det */
+                Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+                Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+                Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+                Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+                Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+                Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+                Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+                Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+                Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+
+                /* physical derivatives psi^Q[i_Q]: d_k phi = sum_m (J^{-1})_{mk} d phi / d xi_m */
+                for (int i = 0; i < ns; ++i) {
+                    psi[i][0] = phi[i][0];
+                    for (int k = 0; k < 3; ++k)
+                        psi[i][1 + k] = Ji[0][k] * phi[i][1] + Ji[1][k] * phi[i][2] +
+                                        Ji[2][k] * phi[i][3];
+                }
+
+                /* coefficients at the point, c^Q[i_Q] */
+                double K[9], bv[3], cc, ff;
+                point_coefficients(mode, rec, field, xq, K, bv, &cc, &ff);
+
+                /* update every entry (i_DOF, j_DOF) with det * w * c^Q * psi * psi */
+                const double dw = det * wq;
+                for (int i = 0; i < ns; ++i) {
+                    for (int j = 0; j < ns; ++j) {
+                        double s = cc * psi[i][0] * psi[j][0];
+                        for (int k = 0; k < 3; ++k)
+                            s += psi[i][0] * bv[k] * psi[j][1 + k];
+                        for (int k = 0; k < 3; ++k)
+                            for (int l = 0; l < 3; ++l)
+                                s += K[k * 3 + l] * psi[i][1 + k] * psi[j][1 + l];
+                        A[(size_t)i * ns + j] += dw * s;
+                    }
+                    if (bvec)
+                        bvec[i] += dw * ff * psi[i][0];
+                }
+            }
+
+    for (size_t t = 0; t < (size_t)ns * ns; ++t)
+        if (!isfinite(A[t]))
+            flags |= ORACLE_FLAG_NONFINITE;
+    return flags;
+}
+
+int oracle_integrate(int64_t nel, int p, const int8_t *degree, const double *geom, int mode,
+                     const double *coef, const double *field, const int64_t *a_off,
+                     const int64_t *b_off, double *out_A, double *out_b, int32_t *flags,
+                     int nthreads)
+{
+    if (nel < 0)
+        return -1;
+    if (nel == 0)
+        return 0;
+    if (!geom || !coef || !out_A)
+        return -1;
+    if (mode != ORACLE_COEF_ELEMENT && mode != ORACLE_COEF_FIELD)
+        return -1;
+    if (mode == ORACLE_COEF_FIELD && !field)
+        return -1;
+    if (degree) {
+        if (!a_off || (out_b && !b_off))
+            return -1;
+        for (int64_t e = 0; e < nel; ++e)
+            if (degree[e] < 1 || degree[e] > 7)
+                return -1;
+    } else if (p < 1 || p > 7) {
+        return -1;
+    }
+    const int rec_len = (mode == ORACLE_COEF_ELEMENT) ? 14 : 10;
+
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t e = 0; e < nel; ++e) {
+        const int pe = degree ? degree[e] : p;
+        const int64_t ns = (int64_t)(pe + 1) * (pe + 1) * (pe + 1);
+        const int64_t ao = a_off ? a_off[e] : e * ns * ns;
+        const int64_t bo = b_off ? b_off[e] : e * ns;
+        int fl = integrate_one(pe, geom + e * 24, mode, coef + e * rec_len, field, out_A + ao,
+                               out_b ? out_b + bo : NULL);
+        if (flags)
+            flags[e] = fl;
+    }
+    return 0;
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

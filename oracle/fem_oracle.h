@@ -1,0 +1,81 @@
+/*
+ * fem_oracle.h -- FP64 CPU oracle for element stiffness-matrix and load-vector integration.
+ *
+ * TEST INFRASTRUCTURE. This library exists to check the HIP path; it is not part of it.
+ * Only the test-suite, the package's smoke check and the benchmark's CPU-baseline leg load it.
+ * It shares no source, header, table or helper with the GPU library.
+ *
+ * What it computes (Banas, Plaszewski, Maciol, "Numerical integration on GPUs for higher order
+ * finite elements", section 2, Algorithm 1 and Algorithm 2; element entry as in eq. (sum_int)
+ * of section 5.1), specialised to one scalar unknown (N_E = 1) and a convection-diffusion-
+ * reaction form:
+ *
+ *   A[i][j] = sum_q w_q detJ_q [ sum_kl K_kl d_k phi_i d_l phi_j
+ *                                + phi_i sum_k b_k d_k phi_j + c phi_i phi_j ]
+ *   b[i]    = sum_q w_q detJ_q f phi_i
+ *
+ * Conventions (readings where the paper is silent):
+ *   reference cube [-1,1]^3; vertex v = v1 + 2 v2 + 4 v3 sits at xi = (2v1-1, 2v2-1, 2v3-1);
+ *   geometry is trilinear from the 8 vertices; shape functions are tensor-product Lagrange
+ *   polynomials on the p+1 Gauss-Lobatto-Legendre nodes, node i = a + n b + n^2 c (n = p+1);
+ *   quadrature is the (p+1)^3 Gauss-Legendre rule, point q = q1 + n q2 + n^2 q3;
+ *   J[a][b] = dx_a/dxi_b, physical gradient = J^{-T} times reference gradient;
+ *   row i of A is the test function, column j the trial function.
+ *
+ * Coefficient records (FP64):
+ *   ELEMENT mode: 14 per element = K (3x3 row-major), b (3), c, f
+ *   FIELD mode:   10 per element = Q (3x3 row-major), f; plus a shared field descriptor of
+ *                 7 fields x 5 modes x (a, k1, k2, k3, theta). Field s at x is
+ *                 g_s(x) = sum_m a_sm sin(2 pi (k_sm . x) + theta_sm); then
+ *                 K = Q diag(10^g0, 10^g1, 10^g2) Q^T, b = (g3, g4, g5), c = (1 + g6)/2.
+ */
+#ifndef FEM_ORACLE_H
+#define FEM_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORACLE_COEF_ELEMENT 0
+#define ORACLE_COEF_FIELD 1
+#define ORACLE_FLAG_DETJ 1     /* detJ <= 0 at one or more quadrature points */
+#define ORACLE_FLAG_NONFINITE 2 /* non-finite input or output */
+
+/* Gauss-Legendre rule with n points on [-1,1], ascending. Returns 0, or -1 if n < 1 or n > 64. */
+int oracle_gauss_legendre(int n, double *x, double *w);
+
+/* The p+1 Gauss-Lobatto-Legendre nodes on [-1,1], ascending. Returns 0, or -1 if p < 1 or p > 63. */
+int oracle_gll_nodes(int p, double *x);
+
+/* Values and first derivatives at x of the n Lagrange polynomials on the given nodes. */
+void oracle_lagrange(int n, const double *nodes, double x, double *val, double *der);
+
+/* The 7 field values g_s at point x (FIELD mode descriptor layout above). */
+void oracle_field_eval(const double *field, const double *x, double *g);
+
+/* Integrate nel elements.
+ *   p        uniform degree 1..7, used when degree == NULL
+ *   degree   per-element degree (1..7) or NULL
+ *   geom     [nel][8][3]
+ *   coef     [nel][14] (ELEMENT) or [nel][10] (FIELD)
+ *   field    175 doubles, FIELD mode only
+ *   a_off    [nel+1] element offsets into out_A, or NULL for e * Ns^2 (uniform p only)
+ *   b_off    [nel+1] element offsets into out_b, or NULL for e * Ns (uniform p only)
+ *   out_A    row-major Ns x Ns per element
+ *   out_b    Ns per element, may be NULL
+ *   flags    [nel] ORACLE_FLAG_* bits per element, may be NULL
+ *   nthreads OpenMP threads, 0 = the runtime default
+ * Returns 0, or -1 on an argument error (nothing is written). */
+int oracle_integrate(int64_t nel, int p, const int8_t *degree, const double *geom, int mode,
+                     const double *coef, const double *field, const int64_t *a_off,
+                     const int64_t *b_off, double *out_A, double *out_b, int32_t *flags,
+                     int nthreads);
+
+/* Number of OpenMP threads a call with nthreads = 0 uses. */
+int oracle_max_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
