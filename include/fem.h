@@ -87,8 +87,9 @@ typedef struct fem_coeffs {
     const int8_t *degree;    /* [nel] per-element degree 1..7 when p == 0, else ignored */
     const int64_t *a_off;    /* [nel+1] element offsets (in entries) into out_A when p == 0 */
     const int64_t *b_off;    /* [nel+1] element offsets into out_b when p == 0 */
-    int32_t *status;         /* [2] or NULL: atomically adds #elements with detJ <= 0 and
-                                #elements with a non-finite input or output */
+    int32_t *status;         /* [2] or NULL: atomically adds #elements where detJ > 0 fails
+                                at some point (NaN included) and #elements with a non-finite
+                                input or output */
     void *workspace;         /* mixed degree only: fem_workspace_bytes(nel) bytes, 256-B aligned */
     size_t workspace_bytes;
 } fem_coeffs;
@@ -118,9 +119,17 @@ size_t fem_workspace_bytes(int64_t nel);
 
 /* Exclusive scans a_off[e] = sum_{e' < e} Ns(e')^2 and b_off[e] = sum_{e' < e} Ns(e') over a
  * device degree array, nel + 1 entries each, computed on the device. `workspace` as for
- * fem_integrate. Degrees outside 1..7 count as 0 entries and are rejected by fem_integrate. */
+ * fem_integrate. Degrees outside 1..7 count as 0 entries; fem_integrate skips such elements. */
 int fem_mixed_offsets(int64_t nel, const int8_t *degree, int64_t *a_off, int64_t *b_off,
                       void *workspace, size_t workspace_bytes, void *stream);
+
+/* HOST copies of the degree-p reference data the kernels use (section 2: quadrature points and
+ * weights, and the 1-D factors of the shape functions): gauss_x[n], gauss_w[n] (the
+ * (p+1)-point Gauss-Legendre rule), lobatto_x[n] (the nodes of the shape functions),
+ * L[q][a] = l_a(gauss_x[q]) and D[q][a] = l_a'(gauss_x[q]), n = p+1. Any pointer may be NULL.
+ * Needs no fem_init and no GPU. Returns FEM_EDEGREE for p outside 1..7. */
+int fem_reference_tables(int p, double *gauss_x, double *gauss_w, double *lobatto_x, double *L,
+                         double *D);
 
 /* Static text for a status code. Never NULL. */
 const char *fem_strerror(int status);

@@ -1,0 +1,365 @@
+// fem_api.cpp -- the C ABI of libfem (declared in include/fem.h): argument validation, the
+// per-degree constant tables (built once in FP64, rounded per precision) and kernel dispatch.
+#include "fem.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "fem_kernel.h"
+#include "fem_layout.h"
+#include "fem_tables.h"
+#include "fem_mixed.h"
+
+namespace fem {
+hipError_t prepare_f64();
+hipError_t prepare_f32();
+hipError_t prepare_bf16();
+hipError_t prepare_split_bf16();
+hipError_t prepare_split_f16();
+hipError_t launch_f64(int p, const KArgs &a, hipStream_t s, int64_t cap);
+hipError_t launch_f32(int p, const KArgs &a, hipStream_t s, int64_t cap);
+hipError_t launch_bf16(int p, const KArgs &a, hipStream_t s, int64_t cap);
+hipError_t launch_split_bf16(int p, const KArgs &a, hipStream_t s, int64_t cap);
+hipError_t launch_split_f16(int p, const KArgs &a, hipStream_t s, int64_t cap);
+}  // namespace fem
+
+namespace {
+
+using namespace fem;
+
+struct DegreeDev {
+    const double *xq = nullptr, *wq = nullptr, *LD64 = nullptr;
+    const float *LD32 = nullptr;
+    const void *row[5][2] = {};
+    float c_bound = 0.0f;
+};
+
+struct State {
+    int device = -1;
+    void *blob = nullptr;  // one device allocation holding every table
+    DegreeDev deg[8];
+};
+State g_state;
+std::mutex g_mutex;
+int64_t g_grid_cap = 2048;  // workgroups of one bucket launch (grid-stride over its work items)
+
+uint16_t bf16_bits_rne(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+double bf16_value(uint16_t h)
+{
+    uint32_t u = uint32_t(h) << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return double(f);
+}
+uint16_t f16_bits(double x)
+{
+    _Float16 h = (_Float16)x;
+    uint16_t b;
+    std::memcpy(&b, &h, 2);
+    return b;
+}
+double f16_value(uint16_t b)
+{
+    _Float16 h;
+    std::memcpy(&h, &b, 2);
+    return double(h);
+}
+
+// Row-operand value of (group g, row block rb, lane, slot v) for family fam, or 0 if padded.
+double row_value(const std::vector<double> &B, int p, int fam, int g, int rb, int lane, int v)
+{
+    const int ns = ns_of(p);
+    const int q = slot_point(fam, g, lane, v);
+    const int r = slot_comp(v);
+    const int i = rb * fam_tm(fam) + lane % fam_tm(fam);
+    if (q >= ns || i >= ns) return 0.0;
+    return B[(size_t(q) * 4 + r) * ns + i];
+}
+
+struct HostBlob {
+    std::vector<unsigned char> bytes;
+    size_t put(const void *src, size_t n)
+    {
+        size_t off = (bytes.size() + 255) & ~size_t(255);
+        bytes.resize(off + n);
+        std::memcpy(bytes.data() + off, src, n);
+        return off;
+    }
+};
+
+int build_tables(State &st)
+{
+    HostBlob hb;
+    struct Offs {
+        size_t xq, wq, ld64, ld32, row[5][2];
+        bool has_lo[5];
+        float c_bound;
+    } offs[8];
+    for (int p = 1; p <= 7; ++p) {
+        HostDegreeTables t = make_degree_tables(p);
+        const int n = t.n;
+        std::vector<double> ld64(n * n * 2);
+        std::vector<float> ld32(n * n * 2);
+        for (int q = 0; q < n; ++q)
+            for (int a = 0; a < n; ++a) {
+                ld64[(q * n + a) * 2] = t.L[q * n + a];
+                ld64[(q * n + a) * 2 + 1] = t.D[q * n + a];
+                ld32[(q * n + a) * 2] = float(t.L[q * n + a]);
+                ld32[(q * n + a) * 2 + 1] = float(t.D[q * n + a]);
+            }
+        Offs &o = offs[p];
+        o.xq = hb.put(t.xq.data(), n * 8);
+        o.wq = hb.put(t.wq.data(), n * 8);
+        o.ld64 = hb.put(ld64.data(), ld64.size() * 8);
+        o.ld32 = hb.put(ld32.data(), ld32.size() * 4);
+        o.c_bound = float(F16_C_TARGET / t.bmax);
+        const std::vector<double> B = reference_operand(t);
+        for (int prec = 0; prec < 5; ++prec) {
+            const int fam = family_of(prec);
+            const int ng = groups_of(p, fam), nrb = rblocks_of(p, fam), sl = fam_slots(fam);
+            const size_t count = size_t(ng) * nrb * 64 * sl;
+            o.has_lo[prec] = false;
+            if (prec == PREC_F64) {
+                std::vector<double> v(count);
+                for (int g = 0; g < ng; ++g)
+                    for (int rb = 0; rb < nrb; ++rb)
+                        for (int l = 0; l < 64; ++l)
+                            for (int s = 0; s < sl; ++s)
+                                v[((size_t(g) * nrb + rb) * 64 + l) * sl + s] = row_value(B, p, fam, g, rb, l, s);
+                o.row[prec][0] = hb.put(v.data(), count * 8);
+            } else if (prec == PREC_F32) {
+                std::vector<float> v(count);
+                for (int g = 0; g < ng; ++g)
+                    for (int rb = 0; rb < nrb; ++rb)
+                        for (int l = 0; l < 64; ++l)
+                            for (int s = 0; s < sl; ++s)
+                                v[((size_t(g) * nrb + rb) * 64 + l) * sl + s] =
+                                    float(row_value(B, p, fam, g, rb, l, s));
+                o.row[prec][0] = hb.put(v.data(), count * 4);
+            } else {
+                std::vector<uint16_t> hi(count), lo(count);
+                for (int g = 0; g < ng; ++g)
+                    for (int rb = 0; rb < nrb; ++rb)
+                        for (int l = 0; l < 64; ++l)
+                            for (int s = 0; s < sl; ++s) {
+                                const size_t idx = ((size_t(g) * nrb + rb) * 64 + l) * sl + s;
+                                const double x = row_value(B, p, fam, g, rb, l, s);
+                                if (prec == PREC_SPLIT_F16) {
+                                    const double y = x * double(F16_TABLE_SCALE);
+                                    hi[idx] = f16_bits(y);
+                                    lo[idx] = f16_bits(y - f16_value(hi[idx]));
+                                } else {
+                                    hi[idx] = bf16_bits_rne(float(x));
+                                    lo[idx] = bf16_bits_rne(float(x - bf16_value(hi[idx])));
+                                }
+                            }
+                o.row[prec][0] = hb.put(hi.data(), count * 2);
+                if (prec != PREC_BF16) {
+                    o.row[prec][1] = hb.put(lo.data(), count * 2);
+                    o.has_lo[prec] = true;
+                }
+            }
+        }
+    }
+    void *d = nullptr;
+    if (hipMalloc(&d, hb.bytes.size()) != hipSuccess) return FEM_ENOMEM;
+    if (hipMemcpy(d, hb.bytes.data(), hb.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return FEM_EHIP;
+    }
+    st.blob = d;
+    unsigned char *base = static_cast<unsigned char *>(d);
+    for (int p = 1; p <= 7; ++p) {
+        const Offs &o = offs[p];
+        DegreeDev &dd = st.deg[p];
+        dd.xq = reinterpret_cast<const double *>(base + o.xq);
+        dd.wq = reinterpret_cast<const double *>(base + o.wq);
+        dd.LD64 = reinterpret_cast<const double *>(base + o.ld64);
+        dd.LD32 = reinterpret_cast<const float *>(base + o.ld32);
+        dd.c_bound = o.c_bound;
+        for (int prec = 0; prec < 5; ++prec) {
+            dd.row[prec][0] = base + o.row[prec][0];
+            dd.row[prec][1] = o.has_lo[prec] ? base + o.row[prec][1] : nullptr;
+        }
+    }
+    return FEM_OK;
+}
+
+}  // namespace
+
+namespace fem {
+hipError_t dispatch(int prec, int p, const KArgs &a, hipStream_t s, int64_t cap)
+{
+    switch (prec) {
+    case PREC_F64: return launch_f64(p, a, s, cap);
+    case PREC_F32: return launch_f32(p, a, s, cap);
+    case PREC_BF16: return launch_bf16(p, a, s, cap);
+    case PREC_SPLIT_BF16: return launch_split_bf16(p, a, s, cap);
+    case PREC_SPLIT_F16: return launch_split_f16(p, a, s, cap);
+    default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace fem
+
+namespace {
+
+KArgs base_args(const fem_coeffs *c, const double *geom, void *out_A, void *out_b)
+{
+    KArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.geom = geom;
+    a.elem = c->elem;
+    a.field = c->mode == FEM_COEF_FIELD ? c->field : nullptr;
+    a.out_A = out_A;
+    a.out_b = out_b;
+    a.status = c->status;
+    a.mode = c->mode;
+    return a;
+}
+
+void set_degree(KArgs &a, int p, int prec)
+{
+    const DegreeDev &d = g_state.deg[p];
+    a.xq = d.xq;
+    a.wq = d.wq;
+    a.LD64 = d.LD64;
+    a.LD32 = d.LD32;
+    a.row_hi = d.row[prec][0];
+    a.row_lo = d.row[prec][1];
+    a.c_bound = d.c_bound;
+    a.row_scale_inv = prec == PREC_SPLIT_F16 ? 1.0f / F16_TABLE_SCALE : 1.0f;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fem_abi_version(void) { return FEM_ABI_VERSION; }
+
+int fem_reference_tables(int p, double *gauss_x, double *gauss_w, double *lobatto_x, double *L,
+                         double *D)
+{
+    if (p < 1 || p > 7) return FEM_EDEGREE;
+    const HostDegreeTables t = make_degree_tables(p);
+    const int n = t.n;
+    if (gauss_x) std::memcpy(gauss_x, t.xq.data(), n * sizeof(double));
+    if (gauss_w) std::memcpy(gauss_w, t.wq.data(), n * sizeof(double));
+    if (lobatto_x) lobatto_nodes(p, lobatto_x);
+    if (L) std::memcpy(L, t.L.data(), n * n * sizeof(double));
+    if (D) std::memcpy(D, t.D.data(), n * n * sizeof(double));
+    return FEM_OK;
+}
+
+const char *fem_strerror(int status)
+{
+    switch (status) {
+    case FEM_OK: return "success";
+    case FEM_EINVAL: return "invalid argument";
+    case FEM_EDEGREE: return "degree outside 1..7 (or p == 0 without a degree array)";
+    case FEM_ENOTINIT: return "fem_init has not been called";
+    case FEM_ENOMEM: return "device allocation failed";
+    case FEM_EHIP: return "HIP runtime error";
+    case FEM_ECONFIG: return "no kernel configuration for this request";
+    case FEM_EWORKSPACE: return "workspace missing or too small";
+    default: return "unknown status";
+    }
+}
+
+int fem_init(int device)
+{
+    std::lock_guard<std::mutex> lock(g_mutex);
+    if (g_state.blob && g_state.device == device) return FEM_OK;
+    if (g_state.blob) return FEM_EINVAL;  // already initialised on another device
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return FEM_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return FEM_EHIP;
+    hipError_t e;
+    if ((e = prepare_f64()) != hipSuccess || (e = prepare_f32()) != hipSuccess ||
+        (e = prepare_bf16()) != hipSuccess || (e = prepare_split_bf16()) != hipSuccess ||
+        (e = prepare_split_f16()) != hipSuccess || (e = mixed_prepare()) != hipSuccess)
+        return FEM_EHIP;
+    const int rc = build_tables(g_state);
+    if (rc != FEM_OK) return rc;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        g_grid_cap = int64_t(prop.multiProcessorCount) * 8;
+    g_state.device = device;
+    return FEM_OK;
+}
+
+int fem_finalize(void)
+{
+    std::lock_guard<std::mutex> lock(g_mutex);
+    if (!g_state.blob) return FEM_ENOTINIT;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(g_state.blob);
+    g_state = State();
+    return FEM_OK;
+}
+
+size_t fem_workspace_bytes(int64_t nel)
+{
+    return nel < 0 ? 0 : mixed_workspace_bytes(nel);
+}
+
+int fem_mixed_offsets(int64_t nel, const int8_t *degree, int64_t *a_off, int64_t *b_off,
+                      void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!g_state.blob) return FEM_ENOTINIT;
+    if (nel < 0 || !a_off || !b_off || (nel > 0 && !degree)) return FEM_EINVAL;
+    if (!workspace || workspace_bytes < mixed_workspace_bytes(nel)) return FEM_EWORKSPACE;
+    return mixed_offsets(nel, degree, a_off, b_off, workspace, (hipStream_t)stream) == hipSuccess
+               ? FEM_OK
+               : FEM_EHIP;
+}
+
+int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coeffs, void *out_A,
+                  void *out_b, void *stream)
+{
+    if (!g_state.blob) return FEM_ENOTINIT;
+    if (nel < 0 || !coeffs) return FEM_EINVAL;
+    if (coeffs->precision < FEM_FP64 || coeffs->precision > FEM_SPLIT_FP16) return FEM_EINVAL;
+    if (coeffs->mode != FEM_COEF_ELEMENT && coeffs->mode != FEM_COEF_FIELD) return FEM_EINVAL;
+    if (p < 0 || p > 7) return FEM_EDEGREE;
+    if (p == 0 && !coeffs->degree) return FEM_EDEGREE;
+    if (nel == 0) return FEM_OK;
+    if (!geom || !out_A || !coeffs->elem) return FEM_EINVAL;
+    if (coeffs->mode == FEM_COEF_FIELD && !coeffs->field) return FEM_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    KArgs a = base_args(coeffs, geom, out_A, out_b);
+    if (p > 0) {
+        a.nel = nel;
+        set_degree(a, p, coeffs->precision);
+        return dispatch(coeffs->precision, p, a, s, int64_t(1) << 30) == hipSuccess ? FEM_OK : FEM_EHIP;
+    }
+    // mixed degree: bucket on the device, then one launch per degree over its bucket
+    if (!coeffs->a_off || (out_b && !coeffs->b_off)) return FEM_EINVAL;
+    if (!coeffs->workspace || coeffs->workspace_bytes < mixed_workspace_bytes(nel)) return FEM_EWORKSPACE;
+    MixedPlan plan;
+    if (mixed_bucket(nel, coeffs->degree, coeffs->workspace, s, &plan) != hipSuccess) return FEM_EHIP;
+    a.a_off = coeffs->a_off;
+    a.b_off = coeffs->b_off;
+    for (int pp = 7; pp >= 1; --pp) {  // heaviest degree first
+        KArgs ap = a;
+        set_degree(ap, pp, coeffs->precision);
+        ap.nel = nel;                  // upper bound; the bucket's count is read on the device
+        ap.elist = plan.elist;
+        ap.seg = plan.seg + 2 * pp;
+        if (dispatch(coeffs->precision, pp, ap, s, g_grid_cap) != hipSuccess) return FEM_EHIP;
+    }
+    return FEM_OK;
+}
+
+}  // extern "C"

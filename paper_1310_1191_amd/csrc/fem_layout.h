@@ -1,0 +1,58 @@
+// fem_layout.h -- the order in which the contraction A = B^T blockdiag(D_q) B is fed to the
+// CDNA4 matrix cores, shared by the host table builder and the kernels.
+//
+// The contraction runs over k = (q, r): quadrature point q and r = 0 (value) or 1..3 (reference
+// derivative), depth 4 N_Q. Each k-group holds KGP consecutive quadrature points. Within a
+// group, lane l of a wave and per-lane slot v address
+//     point = g*KGP + (l / TM) * PPL + v / 4,   r = v % 4,
+// on both operands: the row operand B^T (test function i = rb*TM + l % TM, from a constant
+// table) and the column operand C = D_q B (trial function j, produced per element in registers).
+//
+//   family  instruction (gfx950)          TM  KGP PPL  slots/lane  MFMA per group
+//   MF_K16  v_mfma_f32_32x32x16_{bf16,f16} 32   4   2   8           1 (x3 when split)
+//   MF_F32  v_mfma_f32_32x32x2_f32         32   2   1   4           4 (slot v = step)
+//   MF_F64  v_mfma_f64_16x16x4_f64         16   4   1   4           4 (slot v = step)
+//
+// Row-operand tables are stored [g][rb][lane][slot], one 64-lane fragment per (g, rb), so a
+// wave loads a fragment with one contiguous, fully coalesced access. Padded rows (i >= Ns) and
+// padded points (q >= N_Q) hold zeros.
+#pragma once
+
+#ifdef __HIPCC__
+#define FEM_HD __host__ __device__
+#else
+#define FEM_HD
+#endif
+
+namespace fem {
+
+enum Precision : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_SPLIT_BF16 = 3, PREC_SPLIT_F16 = 4 };
+enum Family : int { MF_K16 = 0, MF_F32 = 1, MF_F64 = 2 };
+
+FEM_HD constexpr int family_of(int prec)
+{
+    return prec == PREC_F64 ? MF_F64 : (prec == PREC_F32 ? MF_F32 : MF_K16);
+}
+FEM_HD constexpr int fam_tm(int fam) { return fam == MF_F64 ? 16 : 32; }
+FEM_HD constexpr int fam_kgp(int fam) { return fam == MF_F32 ? 2 : 4; }
+FEM_HD constexpr int fam_ppl(int fam) { return fam == MF_K16 ? 2 : 1; }
+FEM_HD constexpr int fam_slots(int fam) { return fam == MF_K16 ? 8 : 4; }
+
+FEM_HD constexpr int ns_of(int p) { return (p + 1) * (p + 1) * (p + 1); }
+FEM_HD constexpr int groups_of(int p, int fam) { return (ns_of(p) + fam_kgp(fam) - 1) / fam_kgp(fam); }
+FEM_HD constexpr int rblocks_of(int p, int fam) { return (ns_of(p) + fam_tm(fam) - 1) / fam_tm(fam); }
+
+// Point and component addressed by (group g, lane l, slot v).
+FEM_HD constexpr int slot_point(int fam, int g, int lane, int v)
+{
+    return g * fam_kgp(fam) + (lane / fam_tm(fam)) * fam_ppl(fam) + v / 4;
+}
+FEM_HD constexpr int slot_comp(int v) { return v % 4; }
+
+// Power-of-two scale of the FP16 row-operand table (keeps small entries of B^T out of the FP16
+// subnormal range; every |B| entry stays far below the FP16 maximum for p <= 7).
+constexpr float F16_TABLE_SCALE = 256.0f;
+// The per-element FP16 scale makes max |C| <= 2^15.
+constexpr float F16_C_TARGET = 32768.0f;
+
+}  // namespace fem

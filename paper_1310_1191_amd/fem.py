@@ -1,0 +1,253 @@
+"""Python binding of libfem (include/fem.h): argument marshalling only.
+
+Every step of the integration runs in the HIP kernels of ``libfem.so``; this module turns torch
+device tensors into pointers and calls the C ABI with the same names. There is no CPU fallback:
+if the library is not built, or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfem.so")
+
+FEM_OK = 0
+FEM_EINVAL = -1
+FEM_EDEGREE = -2
+FEM_ENOTINIT = -3
+FEM_ENOMEM = -4
+FEM_EHIP = -5
+FEM_ECONFIG = -6
+FEM_EWORKSPACE = -7
+
+FP64, FP32, BF16, SPLIT_BF16, SPLIT_FP16 = 0, 1, 2, 3, 4
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "split_bf16": SPLIT_BF16,
+              "split_fp16": SPLIT_FP16}
+ELEMENT, FIELD = 0, 1
+
+
+class fem_coeffs(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("mode", ctypes.c_int32),
+        ("elem", ctypes.c_void_p),
+        ("field", ctypes.c_void_p),
+        ("degree", ctypes.c_void_p),
+        ("a_off", ctypes.c_void_p),
+        ("b_off", ctypes.c_void_p),
+        ("status", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class FemError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {fem_strerror(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libfem.so (built in-tree by paper_1310_1191_amd.build). Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1310_1191_amd.build` "
+                           "(there is no fallback path)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.fem_init.argtypes = [ctypes.c_int]
+    lib.fem_finalize.argtypes = []
+    lib.fem_integrate.argtypes = [ctypes.c_int64, ctypes.c_int, vp, ctypes.POINTER(fem_coeffs), vp,
+                                  vp, vp]
+    lib.fem_workspace_bytes.argtypes = [ctypes.c_int64]
+    lib.fem_workspace_bytes.restype = ctypes.c_size_t
+    lib.fem_mixed_offsets.argtypes = [ctypes.c_int64, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.fem_strerror.argtypes = [ctypes.c_int]
+    lib.fem_strerror.restype = ctypes.c_char_p
+    lib.fem_abi_version.argtypes = []
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.fem_reference_tables.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp]
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return ["fem_init", "fem_finalize", "fem_integrate", "fem_workspace_bytes",
+            "fem_mixed_offsets", "fem_reference_tables", "fem_strerror", "fem_abi_version"]
+
+
+# ---------------------------------------------------------------------------------------------
+# the C ABI, one to one
+# ---------------------------------------------------------------------------------------------
+def fem_strerror(status: int) -> str:
+    return load().fem_strerror(int(status)).decode()
+
+
+def fem_abi_version() -> int:
+    return int(load().fem_abi_version())
+
+
+def fem_reference_tables(p: int):
+    """Host copies of the degree-p tables: (gauss_x, gauss_w, lobatto_x, L[q][a], D[q][a])."""
+    import numpy as np
+    n = p + 1
+    gx, gw, lx = np.zeros(n), np.zeros(n), np.zeros(n)
+    L, D = np.zeros((n, n)), np.zeros((n, n))
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = load().fem_reference_tables(int(p), *(a.ctypes.data_as(dp) for a in (gx, gw, lx, L, D)))
+    if rc != FEM_OK:
+        raise FemError(rc, "fem_reference_tables")
+    return gx, gw, lx, L, D
+
+
+def fem_init(device: int = 0) -> None:
+    rc = load().fem_init(int(device))
+    if rc != FEM_OK:
+        raise FemError(rc, "fem_init")
+
+
+def fem_finalize() -> None:
+    rc = load().fem_finalize()
+    if rc != FEM_OK:
+        raise FemError(rc, "fem_finalize")
+
+
+def fem_workspace_bytes(nel: int) -> int:
+    return int(load().fem_workspace_bytes(int(nel)))
+
+
+def fem_integrate(nel: int, p: int, geom: int, coeffs: fem_coeffs, out_A: int, out_b: int | None,
+                  stream: int | None) -> int:
+    """Raw call: integer device addresses, returns the status code."""
+    return int(load().fem_integrate(int(nel), int(p), geom, ctypes.byref(coeffs), out_A, out_b,
+                                    stream))
+
+
+def fem_mixed_offsets(nel: int, degree: int, a_off: int, b_off: int, workspace: int,
+                      workspace_bytes: int, stream: int | None) -> int:
+    return int(load().fem_mixed_offsets(int(nel), degree, a_off, b_off, workspace,
+                                         int(workspace_bytes), stream))
+
+
+# ---------------------------------------------------------------------------------------------
+# torch conveniences (device memory and the current stream only)
+# ---------------------------------------------------------------------------------------------
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libfem needs a ROCm GPU; none is visible")
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check(t, dtype, name):
+    if t is None:
+        return
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} device tensor")
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_coeffs(precision, mode, elem, field=None, degree=None, a_off=None, b_off=None,
+                status=None, workspace=None) -> fem_coeffs:
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    c = fem_coeffs()
+    c.precision = prec
+    c.mode = int(mode)
+    c.elem = elem.data_ptr()
+    c.field = field.data_ptr() if field is not None else None
+    c.degree = degree.data_ptr() if degree is not None else None
+    c.a_off = a_off.data_ptr() if a_off is not None else None
+    c.b_off = b_off.data_ptr() if b_off is not None else None
+    c.status = status.data_ptr() if status is not None else None
+    c.workspace = workspace.data_ptr() if workspace is not None else None
+    c.workspace_bytes = workspace.numel() if workspace is not None else 0
+    return c
+
+
+def out_dtype(precision):
+    torch = _torch()
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return torch.float64 if prec == FP64 else torch.float32
+
+
+def integrate(geom, elem, p: int, precision="split_bf16", mode: int = ELEMENT, field=None,
+              out_A=None, out_b=None, status=None, with_b: bool = True, stream=None):
+    """Uniform degree p: returns (A [nel, Ns, Ns], b [nel, Ns] or None) on the device."""
+    torch = _torch()
+    fem_init(geom.device.index or 0)
+    nel = geom.shape[0]
+    ns = (p + 1) ** 3 if 1 <= p <= 7 else 0
+    dt = out_dtype(precision)
+    _check(geom, torch.float64, "geom")
+    _check(elem, torch.float64, "elem")
+    _check(field, torch.float64, "field")
+    if out_A is None:
+        out_A = torch.empty((nel, ns, ns), dtype=dt, device=geom.device)
+    if out_b is None and with_b:
+        out_b = torch.empty((nel, ns), dtype=dt, device=geom.device)
+    c = make_coeffs(precision, mode, elem, field=field, status=status)
+    rc = fem_integrate(nel, p, _ptr(geom), c, _ptr(out_A), _ptr(out_b), _stream(stream))
+    if rc != FEM_OK:
+        raise FemError(rc, "fem_integrate")
+    return out_A, out_b
+
+
+def mixed_offsets(degree, workspace=None, stream=None):
+    """Device exclusive scans of Ns^2 and Ns over the degrees: (a_off, b_off), nel + 1 each."""
+    torch = _torch()
+    fem_init(degree.device.index or 0)
+    nel = degree.shape[0]
+    _check(degree, torch.int8, "degree")
+    a_off = torch.empty(nel + 1, dtype=torch.int64, device=degree.device)
+    b_off = torch.empty(nel + 1, dtype=torch.int64, device=degree.device)
+    if workspace is None:
+        workspace = torch.empty(fem_workspace_bytes(nel), dtype=torch.uint8, device=degree.device)
+    rc = fem_mixed_offsets(nel, _ptr(degree), _ptr(a_off), _ptr(b_off), _ptr(workspace),
+                           workspace.numel(), _stream(stream))
+    if rc != FEM_OK:
+        raise FemError(rc, "fem_mixed_offsets")
+    return a_off, b_off
+
+
+def integrate_mixed(geom, elem, degree, precision="split_bf16", mode: int = ELEMENT, field=None,
+                    a_off=None, b_off=None, out_A=None, out_b=None, status=None, workspace=None,
+                    with_b: bool = True, stream=None):
+    """Per-element degrees: returns (A packed, b packed, a_off, b_off) on the device."""
+    torch = _torch()
+    fem_init(geom.device.index or 0)
+    nel = geom.shape[0]
+    if workspace is None:
+        workspace = torch.empty(fem_workspace_bytes(nel), dtype=torch.uint8, device=geom.device)
+    if a_off is None or b_off is None:
+        a_off, b_off = mixed_offsets(degree, workspace=workspace, stream=stream)
+        total_a = int(a_off[-1].item())
+        total_b = int(b_off[-1].item())
+    else:
+        total_a = int(a_off[-1].item())
+        total_b = int(b_off[-1].item())
+    dt = out_dtype(precision)
+    if out_A is None:
+        out_A = torch.empty(total_a, dtype=dt, device=geom.device)
+    if out_b is None and with_b:
+        out_b = torch.empty(total_b, dtype=dt, device=geom.device)
+    c = make_coeffs(precision, mode, elem, field=field, degree=degree, a_off=a_off, b_off=b_off,
+                    status=status, workspace=workspace)
+    rc = fem_integrate(nel, 0, _ptr(geom), c, _ptr(out_A), _ptr(out_b), _stream(stream))
+    if rc != FEM_OK:
+        raise FemError(rc, "fem_integrate")
+    return out_A, out_b, a_off, b_off

@@ -1,0 +1,90 @@
+"""The C-ABI library: it loads, exports every function include/fem.h declares, and rejects calls
+made before fem_init without touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fem.h")
+LIB = os.path.join(ROOT, "paper_1310_1191_amd", "libfem.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fem_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libfem.so is not built (run `python -m paper_1310_1191_amd.build`)")
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert {"fem_init", "fem_integrate", "fem_finalize", "fem_strerror"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_wraps_every_symbol():
+    from paper_1310_1191_amd import fem
+    assert sorted(fem.exported_symbols()) == declared_functions()
+
+
+def test_host_only_calls(lib):
+    from paper_1310_1191_amd import fem
+    assert fem.fem_abi_version() == 1
+    assert fem.fem_strerror(0) == "success"
+    assert "init" in fem.fem_strerror(fem.FEM_ENOTINIT)
+    assert fem.fem_strerror(-99) == "unknown status"
+    assert fem.fem_workspace_bytes(-1) == 0
+    a, b = fem.fem_workspace_bytes(1000), fem.fem_workspace_bytes(100000)
+    assert 0 < a < b and a % 256 == 0
+
+
+def test_calls_before_init_are_rejected_on_the_host(lib):
+    from paper_1310_1191_amd import fem
+    c = fem.fem_coeffs()
+    assert fem.fem_integrate(10, 3, None, c, None, None, None) == fem.FEM_ENOTINIT
+    assert fem.fem_mixed_offsets(10, None, None, None, None, 0, None) == fem.FEM_ENOTINIT
+    assert lib.fem_finalize() == fem.FEM_ENOTINIT
+
+
+def test_c_struct_layout_matches_header():
+    from paper_1310_1191_amd import fem
+    # int32, int32, 7 pointers, size_t on LP64
+    assert ctypes.sizeof(fem.fem_coeffs) == 8 + 7 * 8 + 8
+    assert fem.fem_coeffs.elem.offset == 8
+    assert fem.fem_coeffs.workspace_bytes.offset == 8 + 7 * 8
+
+
+@pytest.mark.parametrize("p", range(1, 8))
+def test_library_reference_tables_vs_numpy(p):
+    """The library's own quadrature and Lagrange tables (independent of the oracle's code)
+    against numpy's Gauss-Legendre rule and polynomial algebra."""
+    import numpy as np
+    from numpy.polynomial import legendre as npleg
+
+    from paper_1310_1191_amd import fem
+    from polyexact import gll_nodes_numpy, lagrange_polys
+    gx, gw, lx, L, D = fem.fem_reference_tables(p)
+    xr, wr = npleg.leggauss(p + 1)
+    np.testing.assert_allclose(gx, xr, atol=2e-15)
+    np.testing.assert_allclose(gw, wr, rtol=2e-14)
+    np.testing.assert_allclose(lx, gll_nodes_numpy(p), atol=5e-15)
+    polys = lagrange_polys(gll_nodes_numpy(p))
+    for q in range(p + 1):
+        np.testing.assert_allclose(L[q], [pl(gx[q]) for pl in polys], atol=1e-13)
+        np.testing.assert_allclose(D[q], [pl.deriv()(gx[q]) for pl in polys], atol=1e-11)
+    assert np.isfinite(D).all()
+
+
+def test_reference_tables_reject_bad_degree():
+    from paper_1310_1191_amd import fem
+    with pytest.raises(fem.FemError):
+        fem.fem_reference_tables(8)
