@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Throughput of element stiffness-matrix integration on one MI355X.
+
+One step integrates the whole hot path over the plain-method workload at scale: tensor-product
+Lagrange hexahedra of degree 2, 3 and 4 (27/64/125 shape functions) on jittered structured
+grids of 64x64x64, 64x64x32 and 64x32x32 elements (262144 + 131072 + 65536 elements),
+convection-diffusion-reaction coefficients per element, (p+1)^3 Gauss points, FP32 output.
+Each step runs every stage of the path on the GPU: FP64 Jacobian prologue, point-matrix fold,
+MFMA contraction, load vector and the stores of A and b. Inputs are resident in HBM before
+timing starts; outputs stay on the device.
+
+The reported value is element matrices per second for the split-FP16 contraction (three FP16
+MFMA products per term, FP32 accumulation, <= 1e-6 relative error against the FP64 oracle).
+The same step is also timed with the plain FP32 MFMA path for comparison.
+
+``python bench.py [--steps K] [--warmup W] [--precision split_fp16] [--no-cpu-baseline]``
+prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "split_bf16": 2500.0,
+               "split_fp16": 2500.0}
+PRODUCTS = {"fp64": 1, "fp32": 1, "bf16": 1, "split_bf16": 3, "split_fp16": 3}
+WORKLOAD = [(2, (64, 64, 64)), (3, (64, 64, 32)), (4, (64, 32, 32))]
+
+
+def flops_per_element(p: int) -> float:
+    """Algorithmic work of one element: the contraction 8 Ns^2 NQ plus the load vector 2 Ns NQ."""
+    ns = (p + 1) ** 3
+    return 8.0 * ns * ns * ns + 2.0 * ns * ns
+
+
+def bytes_per_element(p: int, out_bytes: int = 4) -> float:
+    """Algorithmic HBM bytes of one element: 24 FP64 coordinates, a 14-double coefficient record,
+    and the unpadded A (Ns^2) and b (Ns) outputs."""
+    ns = (p + 1) ** 3
+    return 192.0 + 112.0 + (ns * ns + ns) * out_bytes
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(meshes, budget_s: float = 12.0):
+    """The FP64 oracle on the host cores, timed on a bounded sample of the same workload."""
+    import oracle
+    oracle.build(force=False)
+    threads = oracle.max_threads()
+    per_el = {}
+    samples = []
+    for p, geom, coef in meshes:
+        # size the sample so that each degree takes about budget_s / 3 of CPU time
+        probe = min(geom.shape[0], max(threads, 8))
+        t0 = time.perf_counter()
+        oracle.integrate(geom[:probe], coef[:probe], p=p, threads=threads)
+        t_probe = time.perf_counter() - t0
+        n = int(min(geom.shape[0], max(probe, probe * (budget_s / 3.0) / max(t_probe, 1e-6))))
+        t0 = time.perf_counter()
+        oracle.integrate(geom[:n], coef[:n], p=p, threads=threads)
+        dt = time.perf_counter() - t0
+        per_el[p] = dt / n
+        samples.append(f"p={p}: first {n} elements in {dt:.2f} s")
+    total_el = sum(g.shape[0] for _, g, _ in meshes)
+    total_t = sum(per_el[p] * g.shape[0] for p, g, _ in meshes)
+    return {"value": total_el / total_t, "unit": "element matrices/s", "cores": threads,
+            "kind": "oracle", "sample": "; ".join(samples) + " (FP64, OpenMP over elements; "
+            "rate scaled to the full step's element mix)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="split_fp16")
+    ap.add_argument("--compare", default="fp32", help="second path timed for comparison ('' = none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the integration shards "
+              "elements across GPUs without communication, and this build measures one GPU's "
+              "share.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1310_1191_amd import fem, synth
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    dev = torch.device("cuda:0")
+    fem.fem_init(0)
+
+    t0 = time.time()
+    meshes = []
+    for p, grid in WORKLOAD:
+        w = synth.make(2, p=p, grid=grid)
+        meshes.append((p, w.geom, w.coef))
+    log(f"[bench] generated workload in {time.time() - t0:.1f} s: "
+        + ", ".join(f"p={p} nel={g.shape[0]}" for p, g, _ in meshes))
+
+    dev_in = []
+    for p, geom, coef in meshes:
+        g = torch.from_numpy(geom).to(dev)
+        c = torch.from_numpy(coef).to(dev)
+        dev_in.append((p, g, c))
+
+    def run_path(precision, steps, warmup, record_events):
+        dt = fem.out_dtype(precision)
+        outs = []
+        for p, g, c in dev_in:
+            ns = (p + 1) ** 3
+            outs.append((torch.empty((g.shape[0], ns, ns), dtype=dt, device=dev),
+                         torch.empty((g.shape[0], ns), dtype=dt, device=dev)))
+        stream = torch.cuda.current_stream()
+        ev = {p: [] for p, _, _ in dev_in}
+
+        def step(timed):
+            for (p, g, c), (A, b) in zip(dev_in, outs):
+                if timed and record_events:
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                fem.integrate(g, c, p, precision=precision, out_A=A, out_b=b)
+                if timed and record_events:
+                    e1.record(stream)
+                    ev[p].append((e0, e1))
+
+        for _ in range(warmup):
+            step(False)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in range(steps):
+            step(True)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        per_p = {}
+        if record_events:
+            for p in ev:
+                per_p[p] = float(np.mean([a.elapsed_time(b) for a, b in ev[p]]))  # ms
+        del outs
+        torch.cuda.empty_cache()
+        return elapsed, per_p
+
+    log(f"[bench] {args.precision}: warmup {args.warmup}, timing {args.steps} steps")
+    elapsed, per_p = run_path(args.precision, args.steps, args.warmup, True)
+    ms_per_step = elapsed / args.steps * 1e3
+    total_el = sum(g.shape[0] for _, g, _ in dev_in)
+    value = total_el / (elapsed / args.steps)
+    log(f"[bench] {args.precision}: {ms_per_step:.3f} ms/step, {value:.4g} el/s")
+
+    per_degree = {}
+    for p, g, _ in dev_in:
+        t = per_p[p] * 1e-3
+        nel = g.shape[0]
+        fl = flops_per_element(p) * nel / t
+        by = bytes_per_element(p) * nel / t
+        per_degree[str(p)] = {
+            "nel": nel, "ms": round(per_p[p], 4), "el_per_s": nel / t,
+            "tflops": fl / 1e12, "gbs": by / 1e9,
+            "frac_mfma": fl / 1e12 / PEAK_TFLOPS[args.precision],
+            "frac_mfma_executed": fl * PRODUCTS[args.precision] / 1e12 / PEAK_TFLOPS[args.precision],
+            "frac_hbm": by / 1e9 / HBM_PEAK_GBS}
+
+    # dominant kernel: the degree whose launch takes the longest
+    pd = max(per_p, key=lambda p: per_p[p])
+    nel_d = dict((p, g.shape[0]) for p, g, _ in dev_in)[pd]
+    ach_flops = flops_per_element(pd) * nel_d / (per_p[pd] * 1e-3) / 1e12
+    ach_bytes = bytes_per_element(pd) * nel_d / (per_p[pd] * 1e-3) / 1e9
+    # bound: the matrix cores execute PRODUCTS x the algorithmic flops
+    t_mfma = flops_per_element(pd) * PRODUCTS[args.precision] / (PEAK_TFLOPS[args.precision] * 1e12)
+    t_hbm = bytes_per_element(pd) / (HBM_PEAK_GBS * 1e9)
+    if t_mfma >= t_hbm:
+        roof = {"bound": "mfma", "achieved": round(ach_flops, 3),
+                "peak": PEAK_TFLOPS[args.precision], "unit": "TFLOP/s",
+                "frac": round(ach_flops / PEAK_TFLOPS[args.precision], 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(ach_bytes, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach_bytes / HBM_PEAK_GBS, 4)}
+    roof["kernel"] = f"k_integrate p={pd} {args.precision}"
+    roof["launch_ms"] = round(per_p[pd], 4)
+    roof["traffic"] = None
+
+    compare = None
+    if args.compare:
+        csteps = max(3, args.steps // 4)
+        log(f"[bench] comparison path {args.compare}: {csteps} steps")
+        ce, cper = run_path(args.compare, csteps, 1, True)
+        compare = {"precision": args.compare, "ms_per_step": ce / csteps * 1e3,
+                   "el_per_s": total_el / (ce / csteps),
+                   "speedup_of_headline": (ce / csteps) / (elapsed / args.steps),
+                   "per_degree_ms": {str(p): round(v, 4) for p, v in cper.items()}}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU baseline (oracle) on a bounded sample")
+        cpu = cpu_baseline(meshes)
+
+    line = {
+        "metric": "element matrices/s (split-precision MFMA, <= 1e-6 relative error)",
+        "value": value,
+        "unit": "element matrices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"split_fp16": "f16x3->f32", "split_bf16": "bf16x3->f32", "fp32": "f32",
+                  "fp64": "f64", "bf16": "bf16->f32"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "cdr-hex p=2,3,4 on 64x64x64/64x64x32/64x32x32 jittered grids "
+                               "(262144+131072+65536 elements), FP32 output",
+                   "precision": args.precision, "elements_per_step": total_el},
+        "roofline": roof,
+        "per_degree": per_degree,
+        "compare": compare,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
