@@ -123,6 +123,16 @@ size_t fem_workspace_bytes(int64_t nel);
 int fem_mixed_offsets(int64_t nel, const int8_t *degree, int64_t *a_off, int64_t *b_off,
                       void *workspace, size_t workspace_bytes, void *stream);
 
+/* One time step of the coefficient fields, on the device: with t = *step, if 0 <= t < nsteps,
+ * theta_sm += deltas[t][s][m] for the 7 x 5 modes of `field` (reduced to [0, 2 pi)), then
+ * *step = t + 1; otherwise nothing changes. deltas: [nsteps][7][5] FP64 phase increments
+ * supplied by the caller (seeded, drawn on the host); field: the 175-double descriptor of
+ * FEM_COEF_FIELD; step: one int32. All DEVICE pointers. Enqueues one small kernel and neither
+ * allocates nor synchronises, so a stream capture of {fem_field_advance, fem_integrate}
+ * replays as a time-step loop (time-dependent coefficients c^Q of section 2). */
+int fem_field_advance(double *field, const double *deltas, int32_t nsteps, int32_t *step,
+                      void *stream);
+
 /* HOST copies of the degree-p reference data the kernels use (section 2: quadrature points and
  * weights, and the 1-D factors of the shape functions): gauss_x[n], gauss_w[n] (the
  * (p+1)-point Gauss-Legendre rule), lobatto_x[n] (the nodes of the shape functions),
@@ -130,6 +140,40 @@ int fem_mixed_offsets(int64_t nel, const int8_t *degree, int64_t *a_off, int64_t
  * Needs no fem_init and no GPU. Returns FEM_EDEGREE for p outside 1..7. */
 int fem_reference_tables(int p, double *gauss_x, double *gauss_w, double *lobatto_x, double *L,
                          double *D);
+
+/* Kernel variants. Each (p, precision) is compiled in up to FEM_MAX_VARIANTS tile
+ * configurations (elements per workgroup, waves per element, chunk depth of the contraction,
+ * whether the column operand C = D_q B is produced cooperatively in LDS or per wave in
+ * registers, whether the B^T table stays resident in LDS). Which one is fastest depends on p,
+ * the precision and the device; section 4 motivates choosing the work assignment per degree.
+ * fem_integrate launches the variant chosen for its (p, precision): 0 until one of the calls
+ * below chooses another. The choice is process-wide and not thread-safe. */
+#define FEM_MAX_VARIANTS 3
+
+/* Number of variants compiled for (p, precision) (>= 1), FEM_EDEGREE or FEM_EINVAL. */
+int fem_variant_count(int p, int precision);
+
+/* The variant fem_integrate launches for (p, precision), or FEM_EDEGREE / FEM_EINVAL. */
+int fem_get_variant(int p, int precision);
+
+/* Choose the variant for (p, precision); FEM_ECONFIG if variant >= fem_variant_count. Every
+ * variant computes the same result to the precision's tolerance. */
+int fem_set_variant(int p, int precision, int variant);
+
+/* Time every variant of (p, precision) on a seeded synthetic batch of nel elements (element
+ * coefficients, mildly distorted cubes; 1 warm-up and 5 timed launches each, on a stream of
+ * its own), choose the fastest, and, if json_path is not NULL, record the choice and the times
+ * in that HOST file (other entries of an existing file are kept). chosen (HOST, may be NULL)
+ * receives the variant, times_ms (HOST [FEM_MAX_VARIANTS], may be NULL) the mean milliseconds
+ * per launch of each variant. Allocates and frees device memory for the batch and
+ * synchronises; not for use under stream capture. */
+int fem_autotune(int p, int precision, int64_t nel, const char *json_path, int *chosen,
+                 double *times_ms);
+
+/* Apply the choices recorded in a file written by fem_autotune. FEM_ECONFIG if the file was
+ * written on another GPU architecture; entries naming a variant that does not exist are
+ * skipped. applied (HOST, may be NULL) receives the number of choices applied. */
+int fem_load_tuning(const char *json_path, int *applied);
 
 /* Static text for a status code. Never NULL. */
 const char *fem_strerror(int status);

@@ -21,6 +21,7 @@ ARCH = os.environ.get("FEM_OFFLOAD_ARCH", "gfx950")
 HIP_SOURCES = [
     "fem_api.cpp",
     "fem_mixed.hip",
+    "fem_timestep.hip",
     "fem_k_f64.hip",
     "fem_k_f32.hip",
     "fem_k_bf16.hip",

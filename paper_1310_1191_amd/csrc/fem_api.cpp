@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "fem_kernel.h"
@@ -22,11 +23,18 @@ hipError_t prepare_f32();
 hipError_t prepare_bf16();
 hipError_t prepare_split_bf16();
 hipError_t prepare_split_f16();
-hipError_t launch_f64(int p, const KArgs &a, hipStream_t s, int64_t cap);
-hipError_t launch_f32(int p, const KArgs &a, hipStream_t s, int64_t cap);
-hipError_t launch_bf16(int p, const KArgs &a, hipStream_t s, int64_t cap);
-hipError_t launch_split_bf16(int p, const KArgs &a, hipStream_t s, int64_t cap);
-hipError_t launch_split_f16(int p, const KArgs &a, hipStream_t s, int64_t cap);
+hipError_t launch_f64(int p, int v, const KArgs &a, hipStream_t s, int64_t cus);
+hipError_t launch_f32(int p, int v, const KArgs &a, hipStream_t s, int64_t cus);
+hipError_t launch_bf16(int p, int v, const KArgs &a, hipStream_t s, int64_t cus);
+hipError_t launch_split_bf16(int p, int v, const KArgs &a, hipStream_t s, int64_t cus);
+hipError_t launch_split_f16(int p, int v, const KArgs &a, hipStream_t s, int64_t cus);
+int variants_f64(int p);
+int variants_f32(int p);
+int variants_bf16(int p);
+int variants_split_bf16(int p);
+int variants_split_f16(int p);
+hipError_t field_advance(double *field, const double *deltas, int32_t nsteps, int32_t *step,
+                         hipStream_t s);
 }  // namespace fem
 
 namespace {
@@ -47,7 +55,7 @@ struct State {
 };
 State g_state;
 std::mutex g_mutex;
-int64_t g_grid_cap = 2048;  // workgroups of one bucket launch (grid-stride over its work items)
+int64_t g_cus = 256;  // compute units of the device (persistent grids: CUs x resident WGs)
 
 uint16_t bf16_bits_rne(float f)
 {
@@ -128,7 +136,7 @@ int build_tables(State &st)
         const std::vector<double> B = reference_operand(t);
         for (int prec = 0; prec < 5; ++prec) {
             const int fam = family_of(prec);
-            const int ng = groups_of(p, fam), nrb = rblocks_of(p, fam), sl = fam_slots(fam);
+            const int ng = groups_padded(p, fam), nrb = rblocks_of(p, fam), sl = fam_slots(fam);
             const size_t count = size_t(ng) * nrb * 64 * sl;
             o.has_lo[prec] = false;
             if (prec == PREC_F64) {
@@ -200,16 +208,37 @@ int build_tables(State &st)
 }  // namespace
 
 namespace fem {
-hipError_t dispatch(int prec, int p, const KArgs &a, hipStream_t s, int64_t cap)
+int variant_count(int prec, int p)
 {
     switch (prec) {
-    case PREC_F64: return launch_f64(p, a, s, cap);
-    case PREC_F32: return launch_f32(p, a, s, cap);
-    case PREC_BF16: return launch_bf16(p, a, s, cap);
-    case PREC_SPLIT_BF16: return launch_split_bf16(p, a, s, cap);
-    case PREC_SPLIT_F16: return launch_split_f16(p, a, s, cap);
+    case PREC_F64: return variants_f64(p);
+    case PREC_F32: return variants_f32(p);
+    case PREC_BF16: return variants_bf16(p);
+    case PREC_SPLIT_BF16: return variants_split_bf16(p);
+    case PREC_SPLIT_F16: return variants_split_f16(p);
+    default: return 0;
+    }
+}
+
+hipError_t dispatch_variant(int prec, int p, int v, const KArgs &a, hipStream_t s, int64_t cus)
+{
+    switch (prec) {
+    case PREC_F64: return launch_f64(p, v, a, s, cus);
+    case PREC_F32: return launch_f32(p, v, a, s, cus);
+    case PREC_BF16: return launch_bf16(p, v, a, s, cus);
+    case PREC_SPLIT_BF16: return launch_split_bf16(p, v, a, s, cus);
+    case PREC_SPLIT_F16: return launch_split_f16(p, v, a, s, cus);
     default: return hipErrorInvalidValue;
     }
+}
+
+// The variant each (degree, precision) launches: 0 until fem_set_variant, fem_autotune or
+// fem_load_tuning chooses another.
+int g_choice[8][5] = {};
+
+hipError_t dispatch(int prec, int p, const KArgs &a, hipStream_t s, int64_t cus)
+{
+    return dispatch_variant(prec, p, g_choice[p][prec], a, s, cus);
 }
 }  // namespace fem
 
@@ -247,6 +276,15 @@ void set_degree(KArgs &a, int p, int prec)
 extern "C" {
 
 int fem_abi_version(void) { return FEM_ABI_VERSION; }
+
+int fem_field_advance(double *field, const double *deltas, int32_t nsteps, int32_t *step,
+                      void *stream)
+{
+    if (!g_state.blob) return FEM_ENOTINIT;
+    if (!field || !step || nsteps < 0 || (nsteps > 0 && !deltas)) return FEM_EINVAL;
+    return field_advance(field, deltas, nsteps, step, (hipStream_t)stream) == hipSuccess ? FEM_OK
+                                                                                         : FEM_EHIP;
+}
 
 int fem_reference_tables(int p, double *gauss_x, double *gauss_w, double *lobatto_x, double *L,
                          double *D)
@@ -294,7 +332,7 @@ int fem_init(int device)
     if (rc != FEM_OK) return rc;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
-        g_grid_cap = int64_t(prop.multiProcessorCount) * 8;
+        g_cus = prop.multiProcessorCount;
     g_state.device = device;
     return FEM_OK;
 }
@@ -342,7 +380,7 @@ int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coef
     if (p > 0) {
         a.nel = nel;
         set_degree(a, p, coeffs->precision);
-        return dispatch(coeffs->precision, p, a, s, int64_t(1) << 30) == hipSuccess ? FEM_OK : FEM_EHIP;
+        return dispatch(coeffs->precision, p, a, s, g_cus) == hipSuccess ? FEM_OK : FEM_EHIP;
     }
     // mixed degree: bucket on the device, then one launch per degree over its bucket
     if (!coeffs->a_off || (out_b && !coeffs->b_off)) return FEM_EINVAL;
@@ -357,8 +395,221 @@ int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coef
         ap.nel = nel;                  // upper bound; the bucket's count is read on the device
         ap.elist = plan.elist;
         ap.seg = plan.seg + 2 * pp;
-        if (dispatch(coeffs->precision, pp, ap, s, g_grid_cap) != hipSuccess) return FEM_EHIP;
+        if (dispatch(coeffs->precision, pp, ap, s, g_cus) != hipSuccess) return FEM_EHIP;
     }
+    return FEM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Seeded synthetic batch for fem_autotune: independent, mildly distorted unit cubes with an
+// anisotropic SPD diffusion, a small convection and a reaction term (element records), so that
+// every variant runs the same arithmetic it runs on a real mesh.
+struct TuneBatch {
+    std::vector<double> geom, elem;
+};
+TuneBatch tune_batch(int64_t nel)
+{
+    TuneBatch t;
+    t.geom.resize(size_t(nel) * 24);
+    t.elem.assign(size_t(nel) * 14, 0.0);
+    uint64_t x = 0x9e3779b97f4a7c15ull;
+    auto uni = [&x]() {  // xorshift64*, uniform in [-1, 1)
+        x ^= x >> 12; x ^= x << 25; x ^= x >> 27;
+        return double((x * 0x2545f4914f6cdd1dull) >> 11) * 0x1.0p-52 - 1.0;
+    };
+    for (int64_t e = 0; e < nel; ++e) {
+        for (int v = 0; v < 8; ++v)
+            for (int d = 0; d < 3; ++d)
+                t.geom[e * 24 + v * 3 + d] = double((v >> d) & 1) + 0.1 * uni();
+        double *r = &t.elem[e * 14];
+        r[0] = 1.0 + 0.2 * uni(); r[4] = 1.0 + 0.2 * uni(); r[8] = 1.0 + 0.2 * uni();
+        r[1] = r[3] = 0.1 * uni();
+        r[9] = 0.3 * uni(); r[10] = 0.3 * uni(); r[11] = 0.3 * uni();
+        r[12] = 1.0 + 0.5 * uni(); r[13] = uni();
+    }
+    return t;
+}
+
+const char *arch_name()
+{
+    static char name[64] = "";
+    hipDeviceProp_t prop;
+    if (!name[0] && hipGetDeviceProperties(&prop, g_state.device) == hipSuccess) {
+        std::strncpy(name, prop.gcnArchName, sizeof(name) - 1);
+        char *colon = std::strchr(name, ':');
+        if (colon) *colon = '\0';
+    }
+    return name;
+}
+
+struct TuneEntry {
+    int p, precision, variant;
+    double ms[FEM_MAX_VARIANTS];
+    int count;
+};
+
+// Entries of a tuning file. Each entry sits on a line of its own:
+//   {"p": 2, "precision": 4, "variant": 0, "ms": [0.91, 1.02, 1.10]},
+bool read_tuning(const char *path, std::string *arch, std::vector<TuneEntry> *out)
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+        char a[64];
+        if (std::sscanf(line, " {\"arch\": \"%63[^\"]\"", a) == 1) *arch = a;
+        TuneEntry t{};
+        if (std::sscanf(line, " {\"p\": %d, \"precision\": %d, \"variant\": %d", &t.p, &t.precision,
+                        &t.variant) == 3) {
+            const char *m = std::strstr(line, "\"ms\": [");
+            if (m) {
+                m += 7;
+                int used = 0;
+                while (t.count < FEM_MAX_VARIANTS && std::sscanf(m, " %lf%n", &t.ms[t.count], &used) == 1) {
+                    ++t.count;
+                    m += used;
+                    while (*m == ' ' || *m == ',') ++m;
+                }
+            }
+            out->push_back(t);
+        }
+    }
+    std::fclose(f);
+    return true;
+}
+
+bool write_tuning(const char *path, const std::string &arch, const std::vector<TuneEntry> &es)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    std::fprintf(f, "{\"arch\": \"%s\", \"entries\": [\n", arch.c_str());
+    for (size_t k = 0; k < es.size(); ++k) {
+        const TuneEntry &t = es[k];
+        std::fprintf(f, "  {\"p\": %d, \"precision\": %d, \"variant\": %d, \"ms\": [", t.p, t.precision,
+                     t.variant);
+        for (int v = 0; v < t.count; ++v) std::fprintf(f, "%s%.6g", v ? ", " : "", t.ms[v]);
+        std::fprintf(f, "]}%s\n", k + 1 < es.size() ? "," : "");
+    }
+    std::fprintf(f, "]}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fem_variant_count(int p, int precision)
+{
+    if (p < 1 || p > 7) return FEM_EDEGREE;
+    if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16) return FEM_EINVAL;
+    return variant_count(precision, p);
+}
+
+int fem_get_variant(int p, int precision)
+{
+    if (p < 1 || p > 7) return FEM_EDEGREE;
+    if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16) return FEM_EINVAL;
+    return g_choice[p][precision];
+}
+
+int fem_set_variant(int p, int precision, int variant)
+{
+    if (p < 1 || p > 7) return FEM_EDEGREE;
+    if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16) return FEM_EINVAL;
+    if (variant < 0 || variant >= variant_count(precision, p)) return FEM_ECONFIG;
+    g_choice[p][precision] = variant;
+    return FEM_OK;
+}
+
+int fem_autotune(int p, int precision, int64_t nel, const char *json_path, int *chosen,
+                 double *times_ms)
+{
+    if (!g_state.blob) return FEM_ENOTINIT;
+    if (p < 1 || p > 7) return FEM_EDEGREE;
+    if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16 || nel <= 0) return FEM_EINVAL;
+    const int nv = variant_count(precision, p);
+    const int ns = ns_of(p);
+    const size_t osz = precision == FEM_FP64 ? 8 : 4;
+    const TuneBatch tb = tune_batch(nel);
+    void *d_geom = nullptr, *d_elem = nullptr, *d_A = nullptr, *d_b = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int rc = FEM_OK;
+    double best_ms = 0.0;
+    int best = 0;
+    TuneEntry entry{p, precision, 0, {}, nv};
+    auto fail = [&](int code) { if (rc == FEM_OK) rc = code; };
+    if (hipMalloc(&d_geom, tb.geom.size() * 8) != hipSuccess ||
+        hipMalloc(&d_elem, tb.elem.size() * 8) != hipSuccess ||
+        hipMalloc(&d_A, size_t(nel) * ns * ns * osz) != hipSuccess ||
+        hipMalloc(&d_b, size_t(nel) * ns * osz) != hipSuccess)
+        fail(FEM_ENOMEM);
+    if (rc == FEM_OK && (hipStreamCreate(&s) != hipSuccess || hipEventCreate(&ev[0]) != hipSuccess ||
+                         hipEventCreate(&ev[1]) != hipSuccess))
+        fail(FEM_EHIP);
+    if (rc == FEM_OK &&
+        (hipMemcpy(d_geom, tb.geom.data(), tb.geom.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+         hipMemcpy(d_elem, tb.elem.data(), tb.elem.size() * 8, hipMemcpyHostToDevice) != hipSuccess))
+        fail(FEM_EHIP);
+    fem_coeffs c;
+    std::memset(&c, 0, sizeof(c));
+    c.precision = precision;
+    c.mode = FEM_COEF_ELEMENT;
+    c.elem = static_cast<const double *>(d_elem);
+    KArgs a = base_args(&c, static_cast<const double *>(d_geom), d_A, d_b);
+    a.nel = nel;
+    set_degree(a, p, precision);
+    constexpr int REPS = 5;
+    for (int v = 0; v < nv && rc == FEM_OK; ++v) {
+        if (dispatch_variant(precision, p, v, a, s, g_cus) != hipSuccess) { fail(FEM_EHIP); break; }
+        hipEventRecord(ev[0], s);
+        for (int r = 0; r < REPS; ++r)
+            if (dispatch_variant(precision, p, v, a, s, g_cus) != hipSuccess) fail(FEM_EHIP);
+        hipEventRecord(ev[1], s);
+        float ms = 0.0f;
+        if (hipEventSynchronize(ev[1]) != hipSuccess || hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess)
+            fail(FEM_EHIP);
+        entry.ms[v] = double(ms) / REPS;
+        if (times_ms) times_ms[v] = entry.ms[v];
+        if (v == 0 || entry.ms[v] < best_ms) { best_ms = entry.ms[v]; best = v; }
+    }
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    if (ev[1]) (void)hipEventDestroy(ev[1]);
+    if (s) (void)hipStreamDestroy(s);
+    (void)hipFree(d_geom); (void)hipFree(d_elem); (void)hipFree(d_A); (void)hipFree(d_b);
+    if (rc != FEM_OK) return rc;
+    g_choice[p][precision] = best;
+    entry.variant = best;
+    if (chosen) *chosen = best;
+    if (json_path) {
+        std::string arch;
+        std::vector<TuneEntry> es, keep;
+        read_tuning(json_path, &arch, &es);
+        for (const TuneEntry &t : es)
+            if (!(t.p == p && t.precision == precision)) keep.push_back(t);
+        keep.push_back(entry);
+        if (!write_tuning(json_path, arch_name(), keep)) return FEM_EINVAL;
+    }
+    return FEM_OK;
+}
+
+int fem_load_tuning(const char *json_path, int *applied)
+{
+    if (!g_state.blob) return FEM_ENOTINIT;
+    if (!json_path) return FEM_EINVAL;
+    std::string arch;
+    std::vector<TuneEntry> es;
+    if (!read_tuning(json_path, &arch, &es)) return FEM_EINVAL;
+    if (arch != arch_name()) return FEM_ECONFIG;
+    int n = 0;
+    for (const TuneEntry &t : es)
+        if (fem_set_variant(t.p, t.precision, t.variant) == FEM_OK) ++n;
+    if (applied) *applied = n;
     return FEM_OK;
 }
 

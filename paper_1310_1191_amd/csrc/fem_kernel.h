@@ -11,15 +11,17 @@
 //     (rows: test value / derivatives, columns: trial); psi^Q = G phi^Q of section 2 is never
 //     formed. Dh_q and w_q detJ_q f go to LDS.
 //   contraction: A = B^T C with C[(q, r)][j] = sum_s Dh_q[r][s] B[(q, s)][j], a GEMM of depth
-//     4 N_Q on the matrix cores. B^T comes from a constant fragment table; C is produced per
-//     lane in registers from the 1-D Lagrange values L[q][a], D[q][a] (tensor-product structure
-//     of B), in the slot order of fem_layout.h.
-//   load vector: b_i = sum_q w_q detJ_q f phi_i(xi_q), FP64 accumulation.
+//     4 N_Q on the matrix cores. B^T (test functions) is a constant fragment table; C (trial
+//     functions) is produced cooperatively, chunk by chunk, into a double-buffered LDS area from
+//     the 1-D Lagrange values (tensor-product structure of B), while the waves multiply the
+//     previous chunk.
+//   load vector: b_i = sum_q w_q detJ_q f phi_i(xi_q), FP64.
 //   epilogue: accumulators are scaled back (split paths) and stored unpadded, row-major.
 //
-// A workgroup owns one work item = (group of EG elements, row tile, column tile). The columns
-// of a work item are the EG elements' trial functions side by side, NSP apart, so small
-// elements (p = 1, NSP = 8) share one MFMA column block.
+// A workgroup owns work items = (group of EG elements, row tile, column tile) in a persistent
+// grid-stride loop; the next item's element data is fetched while the current one is multiplied.
+// The columns of a work item are the EG elements' trial functions side by side, NSP apart, so
+// small elements (p = 1, NSP = 8) share one MFMA column block.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -36,6 +38,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // Kernel arguments (device pointers). Tables are those of the launch's degree.
 struct KArgs {
@@ -60,14 +66,18 @@ struct KArgs {
     float row_scale_inv;     // 1 / (power-of-two scale of the row table)
 };
 
-template <int EG_, int WGM_, int WGN_, int WM_, int WN_, int OCC_ = 1>
+template <int EG_, int WGM_, int WGN_, int WM_, int WN_, int OCC_, int KC_, int RES_, int PROD_ = 0>
 struct Cfg {
-    static constexpr int OCC = OCC_;  // waves per SIMD the register budget must allow
+    static constexpr int PROD = PROD_;  // 0: C chunks produced by the whole workgroup into LDS;
+                                        // 1: each wave produces its own C fragments in registers
     static constexpr int EG = EG_;    // elements per work item
     static constexpr int WGM = WGM_;  // waves along rows
     static constexpr int WGN = WGN_;  // waves along columns
     static constexpr int WM = WM_;    // row blocks per wave
     static constexpr int WN = WN_;    // column blocks per wave
+    static constexpr int OCC = OCC_;  // waves per SIMD the register budget must allow
+    static constexpr int KC = KC_;    // k-groups per LDS chunk of the column operand
+    static constexpr int RES = RES_;  // 1: the whole row-operand table is kept in LDS
     static constexpr int NW = WGM_ * WGN_;
 };
 
@@ -80,7 +90,12 @@ struct Shape {
     static constexpr int N = P + 1, NS = N * N * N, NQ = NS;
     static constexpr int TM = fam_tm(FAM), KGP = fam_kgp(FAM), PPL = fam_ppl(FAM);
     static constexpr int SLOTS = fam_slots(FAM);
-    static constexpr int NG = groups_of(P, FAM), NQP = NG * KGP;
+    static constexpr int NG = groups_of(P, FAM);
+    static constexpr int KC = C::KC < NG ? C::KC : NG;
+    static_assert(KC == NG || (8 % KC == 0), "chunks of 1, 2, 4 or 8 k-groups, or one chunk");
+    static constexpr int NGP = (NG + KC - 1) / KC * KC;   // <= the table's padded group count
+    static constexpr int NCH = NGP / KC;
+    static constexpr int NQP = NGP * KGP;
     static constexpr int NRB = rblocks_of(P, FAM);
     static constexpr int NSP = (2 * NS <= TM) ? NS : NRB * TM;  // column pitch per element
     static constexpr int EG = C::EG;
@@ -92,20 +107,58 @@ struct Shape {
     static constexpr bool SPLIT = (PREC == PREC_SPLIT_BF16 || PREC == PREC_SPLIT_F16);
     using DT = typename std::conditional<PREC == PREC_F64, double, float>::type;
     static constexpr int DSTR = 16;  // LDS stride of one point matrix (13 used)
+    // column operand chunk: [k-group][column block][part][lane] x FRAGB bytes
+    static constexpr int NCOL = TCB * TM;
+    static_assert(NT % NCOL == 0, "the producers cover the tile's columns");
+    static constexpr int PSTRIDE = NT / NCOL;             // points produced per pass
+    static constexpr int PCH = KC * KGP;                  // points per chunk
+    static constexpr int NPART = SPLIT ? 2 : 1;
+    static constexpr int FRAGB = (PREC == PREC_F64) ? 32 : 16;
+    static constexpr size_t CBUF = C::PROD ? 0 : size_t(KC) * TCB * NPART * 64 * FRAGB;
+    // row operand fragment bytes per lane (both parts)
+    static constexpr int ROWB = (PREC == PREC_F64) ? 32 : (SPLIT ? 32 : 16);
+    static constexpr size_t ROWTAB = C::RES ? size_t(NGP) * NRB * 64 * ROWB : 0;
+    // element data prefetched per thread: 24 coordinates and up to 14 coefficients per element
+    static constexpr int EREC = 38;
+    static constexpr int PFN = (EG * EREC + NT - 1) / NT;
 
-    // dynamic LDS layout (bytes)
+    // dynamic LDS layout (bytes); the point matrices and the column chunks come last so that
+    // the output staging area of the epilogue can overlay them
+    static constexpr size_t al16(size_t x) { return (x + 15) / 16 * 16; }
     static constexpr size_t off_geo = 0;                                  // EG*24 double
     static constexpr size_t off_rec = off_geo + EG * 24 * 8;              // EG*14 double
     static constexpr size_t off_tc = off_rec + EG * 14 * 8;               // EG*24 double
     static constexpr size_t off_fld = off_tc + EG * 24 * 8;               // 176 double
-    static constexpr size_t off_ld64 = off_fld + 176 * 8;                 // N*N*2 double
-    static constexpr size_t off_ld32 = off_ld64 + N * N * 2 * 8;          // N*N*2 float (pad 2)
-    static constexpr size_t off_qw = off_ld32 + ((N * N * 2 * 4 + 15) / 16) * 16;  // 2N double
-    static constexpr size_t off_wf = off_qw + ((2 * N * 8 + 15) / 16) * 16;       // EG*NQP double
-    static constexpr size_t off_D = off_wf + EG * NQP * 8;                         // EG*NQP*16 DT
-    static constexpr size_t off_misc = off_D + size_t(EG) * NQP * DSTR * sizeof(DT);
-    static constexpr size_t lds_bytes = off_misc + EG * 16;  // dmax(u32), flag(i32), sc(f32), unsc(f32)
-    static constexpr int grid_per_group = RT * CT;
+    // 1-D tables, each followed by an all-zero copy of itself (padding columns read zeros)
+    static constexpr size_t off_ld64 = off_fld + 176 * 8;                 // 2 x N*N*2 double
+    static constexpr size_t off_ld32 = off_ld64 + 2 * N * N * 2 * 8;      // 2 x N*N*2 float
+    static constexpr size_t off_qw = off_ld32 + al16(2 * N * N * 2 * 4);  // 2N double
+    static constexpr size_t off_wf = off_qw + al16(2 * N * 8);            // EG*NQP double
+    static constexpr size_t off_misc = off_wf + EG * NQP * 8;             // dmax (u32), flag (i32)
+    static constexpr size_t off_pt = off_misc + al16(EG * 8);             // 3 x NQP int
+    static constexpr size_t off_row = off_pt + al16(3 * NQP * 4);         // resident row table
+    static constexpr size_t off_D = off_row + ROWTAB;                     // EG*NQP*16 DT
+    static constexpr size_t d_bytes = size_t(EG) * NQP * DSTR * sizeof(DT);
+    static constexpr size_t off_cb = off_D + d_bytes;                     // 2 column chunks
+    // Output staging: used when one workgroup owns whole elements (one row and one column
+    // tile); the tile is [NS rows][EG*NSP + 1 columns] of the output type.
+    using OT = DT;
+    static constexpr bool STAGE_OUT = (RT == 1 && CT == 1);
+    static constexpr int OPITCH = EG * NSP + 1;
+    static constexpr size_t out_bytes = STAGE_OUT ? size_t(NS) * OPITCH * sizeof(OT) : 0;
+    static constexpr int NBUF = NCH > 1 ? 2 : 1;
+    // row operand staged per chunk (tables not resident): [k-group][row block][16-B piece][lane]
+    static constexpr int RPART = ROWB / 16;                                 // 16-B pieces per lane
+    static constexpr int RPIECES = C::RES ? 0 : KC * TRB * RPART * 64;
+    static constexpr int RPT = C::RES ? 0 : (RPIECES + NT - 1) / NT;       // pieces per thread
+    static constexpr size_t RBUF = size_t(RPIECES) * 16;
+    static constexpr size_t main_bytes0 = d_bytes + NBUF * (CBUF + RBUF);
+    // the load vector's two EG*NS double temporaries overlay the chunk buffers after the loop
+    static constexpr size_t off_t1 = off_cb, off_t2 = off_cb + EG * NS * 8;
+    static constexpr size_t tmp_bytes = 2 * EG * NS * 8;
+    // the load-vector temporaries live at off_cb after the loop
+    static constexpr size_t main_bytes = main_bytes0 > d_bytes + tmp_bytes ? main_bytes0 : d_bytes + tmp_bytes;
+    static constexpr size_t lds_bytes = off_D + (main_bytes > out_bytes ? main_bytes : out_bytes);
 };
 
 // ------------------------------------------------------------------------------------------
@@ -195,6 +248,35 @@ __device__ inline typename Frag<PREC>::row load_row(const KArgs &a, size_t frag,
     }
 }
 
+// The same with a 32-bit fragment index: the address is a uniform table base plus a 32-bit
+// per-lane byte offset, which the hardware's scalar-base addressing takes directly.
+template <int PREC>
+__device__ inline typename Frag<PREC>::row load_row_off(const KArgs &a, unsigned frag, int lane)
+{
+    constexpr unsigned FB = (PREC == PREC_F64) ? 32u : 16u;
+    const unsigned off = (frag * 64u + (unsigned)lane) * FB;
+    const char *hi = reinterpret_cast<const char *>(a.row_hi);
+    if constexpr (PREC == PREC_F64) {
+        return *reinterpret_cast<const f64x4 *>(hi + off);
+    } else if constexpr (PREC == PREC_F32) {
+        return *reinterpret_cast<const f32x4 *>(hi + off);
+    } else if constexpr (PREC == PREC_BF16) {
+        return *reinterpret_cast<const bf16x8 *>(hi + off);
+    } else if constexpr (PREC == PREC_SPLIT_BF16) {
+        const char *lo = reinterpret_cast<const char *>(a.row_lo);
+        SplitBF r;
+        r.hi = *reinterpret_cast<const bf16x8 *>(hi + off);
+        r.lo = *reinterpret_cast<const bf16x8 *>(lo + off);
+        return r;
+    } else {
+        const char *lo = reinterpret_cast<const char *>(a.row_lo);
+        SplitH r;
+        r.hi = *reinterpret_cast<const f16x8 *>(hi + off);
+        r.lo = *reinterpret_cast<const f16x8 *>(lo + off);
+        return r;
+    }
+}
+
 // Pack the lane's slot values into the column fragment (split: x = hi + lo, both rounded to
 // nearest; lo carries the rounding error of hi).
 template <int PREC, typename T>
@@ -212,18 +294,30 @@ __device__ inline typename Frag<PREC>::col pack_col(const T v[])
         return r;
     } else if constexpr (PREC == PREC_SPLIT_BF16) {
         SplitBF r;
-        for (int t = 0; t < 8; ++t) {
-            const __bf16 h = (__bf16)v[t];
-            r.hi[t] = h;
-            r.lo[t] = (__bf16)(v[t] - (float)h);
+#pragma unroll
+        for (int t = 0; t < 8; t += 2) {
+            const f32x2 x = {v[t], v[t + 1]};
+            const bf16x2 h = __builtin_convertvector(x, bf16x2);
+            const f32x2 hf = __builtin_convertvector(h, f32x2);
+            const bf16x2 l = __builtin_convertvector(x - hf, bf16x2);
+            r.hi[t] = h[0];
+            r.hi[t + 1] = h[1];
+            r.lo[t] = l[0];
+            r.lo[t + 1] = l[1];
         }
         return r;
     } else {
         SplitH r;
-        for (int t = 0; t < 8; ++t) {
-            const _Float16 h = (_Float16)v[t];
-            r.hi[t] = h;
-            r.lo[t] = (_Float16)(v[t] - (float)h);
+#pragma unroll
+        for (int t = 0; t < 8; t += 2) {
+            const f32x2 x = {v[t], v[t + 1]};
+            const f16x2 h = __builtin_convertvector(x, f16x2);
+            const f32x2 hf = __builtin_convertvector(h, f32x2);
+            const f16x2 l = __builtin_convertvector(x - hf, f16x2);
+            r.hi[t] = h[0];
+            r.hi[t + 1] = h[1];
+            r.lo[t] = l[0];
+            r.lo[t + 1] = l[1];
         }
         return r;
     }
@@ -252,6 +346,26 @@ __device__ inline void mma(typename Frag<PREC>::acc &c, const typename Frag<PREC
     }
 }
 
+// One of the products of the split paths (stage 0: lo*hi, 1: hi*lo, 2: hi*hi); the unsplit
+// paths do all their work in stage 0. Issuing a stage for every accumulator before the next
+// stage keeps independent MFMAs back to back.
+template <int PREC, int STAGE>
+__device__ inline void mma_stage(typename Frag<PREC>::acc &c, const typename Frag<PREC>::row &a,
+                                 const typename Frag<PREC>::col &b)
+{
+    if constexpr (PREC == PREC_SPLIT_BF16) {
+        if constexpr (STAGE == 0) c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.lo, b.hi, c, 0, 0, 0);
+        if constexpr (STAGE == 1) c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.hi, b.lo, c, 0, 0, 0);
+        if constexpr (STAGE == 2) c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.hi, b.hi, c, 0, 0, 0);
+    } else if constexpr (PREC == PREC_SPLIT_F16) {
+        if constexpr (STAGE == 0) c = __builtin_amdgcn_mfma_f32_32x32x16_f16(a.lo, b.hi, c, 0, 0, 0);
+        if constexpr (STAGE == 1) c = __builtin_amdgcn_mfma_f32_32x32x16_f16(a.hi, b.lo, c, 0, 0, 0);
+        if constexpr (STAGE == 2) c = __builtin_amdgcn_mfma_f32_32x32x16_f16(a.hi, b.hi, c, 0, 0, 0);
+    } else if constexpr (STAGE == 0) {
+        mma<PREC>(c, a, b);
+    }
+}
+
 // Row of accumulator entry v held by `lane` (column is lane % TM). The FP64 16x16 result holds
 // row lane/16 + 4v; the 32x32 FP32-accumulator results hold row 8(v/4) + 4(lane/32) + v%4.
 template <int FAM>
@@ -262,11 +376,162 @@ __device__ inline int acc_row(int lane, int v)
 }
 
 // ------------------------------------------------------------------------------------------
-// the kernel
+// column-operand chunk access
 // ------------------------------------------------------------------------------------------
+// Largest power of two sc with sc * max|Dh| * bmax <= 2^15 (max|C| then fits FP16), i.e.
+// sc <= c_bound / max|Dh|. Every thread that needs it recomputes it from the element maximum.
+__device__ inline float split_scale(unsigned dmax_bits, float c_bound)
+{
+    const float dm = __uint_as_float(dmax_bits);
+    if (!(dm > 0.0f)) return 1.0f;
+    float ratio = c_bound / dm;
+    ratio = ratio < 1e30f ? ratio : 1e30f;
+    int ex;
+    frexpf(ratio, &ex);  // 2^(ex-1) <= ratio < 2^ex
+    int e2 = ex - 1;
+    e2 = e2 > 120 ? 120 : (e2 < -120 ? -120 : e2);
+    return ldexpf(1.0f, e2);
+}
+
+// Store the 4 values (r = 0..3) of one (point, column) pair into a column chunk. `kgl` is the
+// k-group within the chunk, `w` the point within the k-group, `c` the column within the tile.
+template <int PREC, class S, typename T>
+__device__ inline void put_col(unsigned char *buf, int kgl, int w, int c, const T v[4])
+{
+    constexpr int TM = S::TM;
+    const int h = w / S::PPL, sub = w % S::PPL;
+    const int lane = (c % TM) + TM * h;
+    const int cbt = c / TM;
+    const size_t frag = (size_t)(kgl * S::TCB + cbt) * S::NPART;
+    if constexpr (PREC == PREC_F64) {
+        f64x2 *d = reinterpret_cast<f64x2 *>(buf + (frag * 64 + lane) * 32);
+        d[0] = f64x2{v[0], v[1]};
+        d[1] = f64x2{v[2], v[3]};
+    } else if constexpr (PREC == PREC_F32) {
+        *reinterpret_cast<f32x4 *>(buf + (frag * 64 + lane) * 16) = f32x4{v[0], v[1], v[2], v[3]};
+    } else {
+        typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+        const f32x2 x01 = {v[0], v[1]}, x23 = {v[2], v[3]};
+        unsigned char *p = buf + (frag * 64 + lane) * 16 + sub * 8;
+        if constexpr (PREC == PREC_BF16) {
+            const bf16x2 h01 = __builtin_convertvector(x01, bf16x2);
+            const bf16x2 h23 = __builtin_convertvector(x23, bf16x2);
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            *reinterpret_cast<bf16x4 *>(p) = bf16x4{h01[0], h01[1], h23[0], h23[1]};
+        } else if constexpr (PREC == PREC_SPLIT_BF16) {
+            const bf16x2 h01 = __builtin_convertvector(x01, bf16x2);
+            const bf16x2 h23 = __builtin_convertvector(x23, bf16x2);
+            const bf16x2 l01 = __builtin_convertvector(x01 - __builtin_convertvector(h01, f32x2), bf16x2);
+            const bf16x2 l23 = __builtin_convertvector(x23 - __builtin_convertvector(h23, f32x2), bf16x2);
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            *reinterpret_cast<bf16x4 *>(p) = bf16x4{h01[0], h01[1], h23[0], h23[1]};
+            *reinterpret_cast<bf16x4 *>(p + 64 * 16) = bf16x4{l01[0], l01[1], l23[0], l23[1]};
+        } else {
+            const f16x2 h01 = __builtin_convertvector(x01, f16x2);
+            const f16x2 h23 = __builtin_convertvector(x23, f16x2);
+            const f16x2 l01 = __builtin_convertvector(x01 - __builtin_convertvector(h01, f32x2), f16x2);
+            const f16x2 l23 = __builtin_convertvector(x23 - __builtin_convertvector(h23, f32x2), f16x2);
+            typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+            *reinterpret_cast<f16x4 *>(p) = f16x4{h01[0], h01[1], h23[0], h23[1]};
+            *reinterpret_cast<f16x4 *>(p + 64 * 16) = f16x4{l01[0], l01[1], l23[0], l23[1]};
+        }
+    }
+}
+
+// A wave's column fragment of column block cbt (within the tile) and k-group kgl of a chunk.
+template <int PREC, class S>
+__device__ inline typename Frag<PREC>::col get_col(const unsigned char *buf, int kgl, int cbt, int lane)
+{
+    const size_t frag = (size_t)(kgl * S::TCB + cbt) * S::NPART;
+    if constexpr (PREC == PREC_F64) {
+        return *reinterpret_cast<const f64x4 *>(buf + (frag * 64 + lane) * 32);
+    } else if constexpr (PREC == PREC_F32) {
+        return *reinterpret_cast<const f32x4 *>(buf + (frag * 64 + lane) * 16);
+    } else if constexpr (PREC == PREC_BF16) {
+        return *reinterpret_cast<const bf16x8 *>(buf + (frag * 64 + lane) * 16);
+    } else if constexpr (PREC == PREC_SPLIT_BF16) {
+        SplitBF r;
+        r.hi = *reinterpret_cast<const bf16x8 *>(buf + (frag * 64 + lane) * 16);
+        r.lo = *reinterpret_cast<const bf16x8 *>(buf + ((frag + 1) * 64 + lane) * 16);
+        return r;
+    } else {
+        SplitH r;
+        r.hi = *reinterpret_cast<const f16x8 *>(buf + (frag * 64 + lane) * 16);
+        r.lo = *reinterpret_cast<const f16x8 *>(buf + ((frag + 1) * 64 + lane) * 16);
+        return r;
+    }
+}
+
+// Row fragment from the LDS-resident copy of the table (layout [frag][part][lane] x 16 B, or
+// [frag][lane] x 32 B for FP64).
+template <int PREC>
+__device__ inline typename Frag<PREC>::row lds_row(const unsigned char *tab, size_t frag, int lane)
+{
+    if constexpr (PREC == PREC_F64) {
+        return *reinterpret_cast<const f64x4 *>(tab + (frag * 64 + lane) * 32);
+    } else if constexpr (PREC == PREC_F32) {
+        return *reinterpret_cast<const f32x4 *>(tab + (frag * 64 + lane) * 16);
+    } else if constexpr (PREC == PREC_BF16) {
+        return *reinterpret_cast<const bf16x8 *>(tab + (frag * 64 + lane) * 16);
+    } else if constexpr (PREC == PREC_SPLIT_BF16) {
+        SplitBF r;
+        r.hi = *reinterpret_cast<const bf16x8 *>(tab + (frag * 128 + lane) * 16);
+        r.lo = *reinterpret_cast<const bf16x8 *>(tab + (frag * 128 + 64 + lane) * 16);
+        return r;
+    } else {
+        SplitH r;
+        r.hi = *reinterpret_cast<const f16x8 *>(tab + (frag * 128 + lane) * 16);
+        r.lo = *reinterpret_cast<const f16x8 *>(tab + (frag * 128 + 64 + lane) * 16);
+        return r;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// one work item
+// ------------------------------------------------------------------------------------------
+struct Item {
+    int64_t e0;  // first element index (into elist, or the element id itself)
+    int neg;     // elements present (<= EG)
+    int rt, ct;  // row and column tile
+};
+
+template <class S>
+__device__ inline Item decode_item(int64_t wi, int64_t nel)
+{
+    Item it;
+    it.ct = (int)(wi % S::CT);
+    wi /= S::CT;
+    it.rt = (int)(wi % S::RT);
+    it.e0 = (wi / S::RT) * S::EG;
+    it.neg = (int)((nel - it.e0) < S::EG ? (nel - it.e0) : S::EG);
+    return it;
+}
+
+// Fetch the element data of an item into registers (24 coordinates then the coefficient record
+// of each element; entries past the record length or the element count are 0).
+template <class S>
+__device__ inline void fetch_elements(const KArgs &a, const int32_t *elist, const Item &it,
+                                      int reclen, double (&pf)[S::PFN])
+{
+#pragma unroll
+    for (int k = 0; k < S::PFN; ++k) {
+        const int f = threadIdx.x + k * S::NT;
+        const int el = f / S::EREC, comp = f % S::EREC;
+        double v = 0.0;
+        if (el < it.neg) {
+            const int64_t e = element_id(elist, it.e0 + el);
+            if (comp < 24) v = a.geom[e * 24 + comp];
+            else if (comp - 24 < reclen) v = a.elem[e * reclen + (comp - 24)];
+        }
+        pf[k] = v;
+    }
+}
+
 template <int P, int PREC, class C>
-__device__ inline void integrate_item(const KArgs &a, int64_t wi, const int64_t nel,
-                                      const int32_t *elist, unsigned char *smem)
+__device__ inline void integrate_item(const KArgs &a, const Item &it, const int32_t *elist,
+                                      int reclen, unsigned char *smem, const double (&pf)[Shape<P, PREC, C>::PFN],
+                                      double (&pf_next)[Shape<P, PREC, C>::PFN], bool has_next,
+                                      const Item &it_next)
 {
     using S = Shape<P, PREC, C>;
     using DT = typename S::DT;
@@ -279,42 +544,33 @@ __device__ inline void integrate_item(const KArgs &a, int64_t wi, const int64_t 
     double *s_tc = reinterpret_cast<double *>(smem + S::off_tc);
     double *s_fld = reinterpret_cast<double *>(smem + S::off_fld);
     double *s_ld64 = reinterpret_cast<double *>(smem + S::off_ld64);
-    float *s_ld32 = reinterpret_cast<float *>(smem + S::off_ld32);
     double *s_qw = reinterpret_cast<double *>(smem + S::off_qw);
     double *s_wf = reinterpret_cast<double *>(smem + S::off_wf);
-    DT *s_D = reinterpret_cast<DT *>(smem + S::off_D);
+    double *s_t1 = reinterpret_cast<double *>(smem + S::off_t1);
+    double *s_t2 = reinterpret_cast<double *>(smem + S::off_t2);
     unsigned *s_dmax = reinterpret_cast<unsigned *>(smem + S::off_misc);
     int *s_flag = reinterpret_cast<int *>(smem + S::off_misc + EG * 4);
-    float *s_sc = reinterpret_cast<float *>(smem + S::off_misc + EG * 8);
-    float *s_unsc = reinterpret_cast<float *>(smem + S::off_misc + EG * 12);
+    int *s_pt = reinterpret_cast<int *>(smem + S::off_pt);
+    const unsigned char *s_row = smem + S::off_row;
+    DT *s_D = reinterpret_cast<DT *>(smem + S::off_D);
+    unsigned char *s_cb0 = smem + S::off_cb;
+    unsigned char *s_cb1 = smem + S::off_cb + S::CBUF;
+    unsigned char *s_rb0 = smem + S::off_cb + S::NBUF * S::CBUF;
+    unsigned char *s_rb1 = s_rb0 + S::RBUF;
 
     const int tid = threadIdx.x;
-    const int ct = (int)(wi % S::CT);
-    wi /= S::CT;
-    const int rt = (int)(wi % S::RT);
-    const int64_t grp = wi / S::RT;
-    const int64_t e0 = grp * EG;
-    const int neg = (int)((nel - e0) < EG ? (nel - e0) : EG);
-    const int reclen = a.mode == 0 ? 14 : 10;
+    const int neg = it.neg, rt = it.rt, ct = it.ct;
+    const int64_t e0 = it.e0;
 
-    // ---- element data, tables and field descriptor into LDS ----
-    for (int t = tid; t < EG * 24; t += NT) {
-        const int el = t / 24, c = t % 24;
-        s_geo[t] = el < neg ? a.geom[element_id(elist, e0 + el) * 24 + c] : 0.0;
-    }
-    for (int t = tid; t < EG * 14; t += NT) {
-        const int el = t / 14, c = t % 14;
-        s_rec[t] = (el < neg && c < reclen) ? a.elem[element_id(elist, e0 + el) * reclen + c] : 0.0;
-    }
-    if (a.mode == 1)
-        for (int t = tid; t < 175; t += NT) s_fld[t] = a.field[t];
-    for (int t = tid; t < N * N * 2; t += NT) {
-        s_ld64[t] = a.LD64[t];
-        s_ld32[t] = a.LD32[t];
-    }
-    for (int t = tid; t < N; t += NT) {
-        s_qw[t] = a.xq[t];
-        s_qw[N + t] = a.wq[t];
+    // ---- element data (fetched earlier) into LDS ----
+#pragma unroll
+    for (int k = 0; k < S::PFN; ++k) {
+        const int f = tid + k * NT;
+        const int el = f / S::EREC, comp = f % S::EREC;
+        if (el < EG) {
+            if (comp < 24) s_geo[el * 24 + comp] = pf[k];
+            else s_rec[el * 14 + (comp - 24)] = pf[k];
+        }
     }
     if (tid < EG) {
         s_dmax[tid] = 0u;
@@ -472,60 +728,102 @@ __device__ inline void integrate_item(const KArgs &a, int64_t wi, const int64_t 
     }
     __syncthreads();
 
-    if (tid < EG) {
-        float sc = 1.0f;
-        if (S::SPLIT) {
-            // largest power of two sc with sc * max|Dh| * bmax <= 2^15, i.e. sc <= c_bound / max|Dh|
-            const float dm = __uint_as_float(s_dmax[tid]);
-            if (dm > 0.0f) {
-                float ratio = a.c_bound / dm;
-                ratio = ratio < 1e30f ? ratio : 1e30f;
-                int ex;
-                frexpf(ratio, &ex);  // 2^(ex-1) <= ratio < 2^ex
-                int e2 = ex - 1;
-                e2 = e2 > 120 ? 120 : (e2 < -120 ? -120 : e2);
-                sc = ldexpf(1.0f, e2);
-            }
-        }
-        s_sc[tid] = sc;
-        s_unsc[tid] = a.row_scale_inv / sc;
-        if (rt == 0 && ct == 0 && a.status && tid < neg) {
-            const int fl = s_flag[tid];
-            if (fl & 1) atomicAdd(&a.status[0], 1);
-            if (fl & 2) atomicAdd(&a.status[1], 1);
-        }
+    if (tid < neg && rt == 0 && ct == 0 && a.status) {
+        const int fl = s_flag[tid];
+        if (fl & 1) atomicAdd(&a.status[0], 1);
+        if (fl & 2) atomicAdd(&a.status[1], 1);
     }
-    __syncthreads();
-    if (S::SPLIT) {
-        for (int t = tid; t < EG * NQP * S::DSTR; t += NT) s_D[t] *= s_sc[t / (NQP * S::DSTR)];
+    if constexpr (S::SPLIT) {
+        // exact power-of-two scaling of each element's point matrices (FP16 range)
+#pragma unroll 1
+        for (int t = tid; t < EG * NQP; t += NT) {
+            const DT sc = DT(split_scale(s_dmax[t / NQP], a.c_bound));
+            DT *Dr = s_D + (size_t)t * S::DSTR;
+#pragma unroll
+            for (int u = 0; u < 13; ++u) Dr[u] *= sc;
+        }
         __syncthreads();
     }
 
-    // ---- contraction on the matrix cores ----
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wm = wave / C::WGN, wn = wave % C::WGN;
-    const int rb0 = rt * S::TRB + wm * C::WM;
-    const int cb0 = ct * S::TCB + wn * C::WN;
-    const DT *ld = nullptr;
-    if constexpr (PREC == PREC_F64) ld = s_ld64; else ld = s_ld32;
+    // the element data of the next item travels while this one is multiplied
+    if (has_next) fetch_elements<S>(a, elist, it_next, reclen, pf_next);
 
-    int col_el[C::WN], col_a[C::WN], col_b[C::WN], col_c[C::WN];
-    bool col_ok[C::WN];
-#pragma unroll
-    for (int j = 0; j < C::WN; ++j) {
-        const int cb = cb0 + j;
-        const int col = cb * TM + (lane % TM);
+    // ---- producer setup: this thread's column of the tile ----
+    using DT2 = typename std::conditional<PREC == PREC_F64, f64x2, f32x2>::type;
+    const DT2 *ld2 = nullptr;
+    if constexpr (PREC == PREC_F64) ld2 = reinterpret_cast<const DT2 *>(s_ld64);
+    else ld2 = reinterpret_cast<const DT2 *>(smem + S::off_ld32);
+    const int pc = tid % S::NCOL;
+    const int pp0 = tid / S::NCOL;
+    int p_el, p_a, p_b, p_c;
+    bool p_ok;
+    {
+        const int cbg = ct * S::TCB + pc / TM;
+        const int col = cbg * TM + pc % TM;
         const int el = col / S::NSP, jj = col % S::NSP;
-        col_ok[j] = (cb < S::NCB) && (jj < NS) && (el < neg);
-        const int jc = col_ok[j] ? jj : 0;
-        col_el[j] = (cb < S::NCB) ? el : 0;
-        col_a[j] = jc % N;
-        col_b[j] = (jc / N) % N;
-        col_c[j] = jc / (N * N);
+        p_ok = cbg < S::NCB && jj < NS && el < neg;
+        const int jc = (p_ok ? jj : 0);
+        p_el = (cbg < S::NCB) ? el : 0;
+        p_a = jc % N;
+        p_b = (jc / N) % N;
+        p_c = jc / (N * N);
     }
-    bool row_ok[C::WM];
+
+    // A production unit owns one lane slot of a column fragment: column c of the tile and the
+    // PPL points of lane group h in k-group kgl, written as whole 16-byte pieces.
+    constexpr int HPG = S::KGP / S::PPL;
+    constexpr int UNITS = S::KC * HPG * S::NCOL;
+    static_assert(NT % S::NCOL == 0, "producer columns are fixed per thread");
+    const unsigned char *ldb = reinterpret_cast<const unsigned char *>(ld2);
+    // padding columns read the first-direction factor from the zero copy of the table
+    const int p_ab = (p_a + (p_ok ? 0 : N * N)) * (int)sizeof(DT2);
+    const int p_bb = p_b * (int)sizeof(DT2), p_cb = p_c * (int)sizeof(DT2);
+    const DT *Dbase = s_D + (size_t)p_el * NQP * S::DSTR;
+    auto produce_chunk = [&](int ch, unsigned char *buf) {
 #pragma unroll
-    for (int i = 0; i < C::WM; ++i) row_ok[i] = (rb0 + i) < S::NRB;
+        for (int u = tid; u < UNITS; u += NT) {
+            const int h = (u / S::NCOL) % HPG, kgl = u / (S::NCOL * HPG);
+            DT vals[S::SLOTS];
+#pragma unroll
+            for (int sub = 0; sub < S::PPL; ++sub) {
+                const int q = (ch * S::KC + kgl) * S::KGP + h * S::PPL + sub;
+                const DT *Dh = Dbase + q * S::DSTR;
+                DT dloc[13];
+#pragma unroll
+                for (int uu = 0; uu < 13; ++uu) dloc[uu] = Dh[uu];
+                const DT2 fa = *reinterpret_cast<const DT2 *>(ldb + s_pt[q] + p_ab);
+                const DT2 fb = *reinterpret_cast<const DT2 *>(ldb + s_pt[NQP + q] + p_bb);
+                const DT2 fc = *reinterpret_cast<const DT2 *>(ldb + s_pt[2 * NQP + q] + p_cb);
+                DT out[4];
+                column_values<DT>(dloc, fa[0], fa[1], fb[0], fb[1], fc[0], fc[1], out);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) vals[sub * 4 + r] = out[r];
+            }
+            const int lane_s = (pc % TM) + TM * h;
+            const size_t frag = (size_t)(kgl * S::TCB + pc / TM) * S::NPART;
+            const typename F::col cf = pack_col<PREC, DT>(vals);
+            if constexpr (PREC == PREC_F64) {
+                *reinterpret_cast<f64x4 *>(buf + (frag * 64 + lane_s) * 32) = cf;
+            } else if constexpr (PREC == PREC_F32 || PREC == PREC_BF16) {
+                *reinterpret_cast<typename F::col *>(buf + (frag * 64 + lane_s) * 16) = cf;
+            } else {
+                *reinterpret_cast<decltype(cf.hi) *>(buf + (frag * 64 + lane_s) * 16) = cf.hi;
+                *reinterpret_cast<decltype(cf.lo) *>(buf + ((frag + 1) * 64 + lane_s) * 16) = cf.lo;
+            }
+        }
+    };
+
+    // ---- consumer setup ----
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = C::WGM == 1 ? 0 : wave / C::WGN, wn = C::WGN == 1 ? 0 : wave % C::WGN;
+    const int rb0 = (S::RT == 1 ? 0 : rt * S::TRB) + wm * C::WM;
+    const int cbt0 = wn * C::WN;    // first column block of the wave within the tile
+    // Row blocks past the element's last block (ragged tiles) recompute the last valid block;
+    // their results are never stored.
+    int rbl[C::WM];
+#pragma unroll
+    for (int i = 0; i < C::WM; ++i) rbl[i] = (rb0 + i) < S::NRB ? (rb0 + i) : (S::NRB - 1);
 
     typename F::acc acc[C::WM][C::WN];
 #pragma unroll
@@ -535,105 +833,325 @@ __device__ inline void integrate_item(const KArgs &a, int64_t wi, const int64_t 
 #pragma unroll
             for (int v = 0; v < F::ACC_N; ++v) acc[i][j][v] = 0;
 
-    const int half = lane / TM;
-#pragma unroll 1
-    for (int g = 0; g < S::NG; ++g) {
-        typename F::row ra[C::WM];
+    // row operand of chunk ch: fetched from the global table into registers a chunk ahead, then
+    // written to an LDS buffer; the resident variant reads the whole table from LDS
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 rstage[S::RPT > 0 ? S::RPT : 1];
+    const int rbT0 = S::RT == 1 ? 0 : rt * S::TRB;
+    auto fetch_rows = [&](int ch) {
+        if constexpr (!C::RES) {
+            const u32x4 *hi = reinterpret_cast<const u32x4 *>(a.row_hi);
+            const u32x4 *lo = reinterpret_cast<const u32x4 *>(a.row_lo);
+#pragma unroll
+            for (int k = 0; k < S::RPT; ++k) {
+                const int piece = tid + k * NT;
+                if (S::RPIECES % NT == 0 || piece < S::RPIECES) {
+                    const int l = piece % 64, part = (piece / 64) % S::RPART;
+                    const int rbt = (piece / (64 * S::RPART)) % S::TRB, kgl = piece / (64 * S::RPART * S::TRB);
+                    const int rb = (rbT0 + rbt) < S::NRB ? (rbT0 + rbt) : (S::NRB - 1);
+                    const unsigned frag = (unsigned)((ch * S::KC + kgl) * S::NRB + rb);
+                    if constexpr (S::SPLIT) rstage[k] = (part ? lo : hi)[frag * 64u + l];
+                    else rstage[k] = hi[(frag * 64u + l) * S::RPART + part];
+                }
+            }
+        }
+    };
+    auto store_rows = [&](unsigned char *rbuf) {
+        if constexpr (!C::RES) {
+#pragma unroll
+            for (int k = 0; k < S::RPT; ++k) {
+                const int piece = tid + k * NT;
+                if (S::RPIECES % NT == 0 || piece < S::RPIECES) {
+                    const int l = piece % 64, part = (piece / 64) % S::RPART;
+                    const int frag = piece / (64 * S::RPART);
+                    // LDS piece layout: [frag][lane][part] so that one lane's pieces are adjacent
+                    reinterpret_cast<u32x4 *>(rbuf)[(frag * 64 + l) * S::RPART + part] = rstage[k];
+                }
+            }
+        }
+    };
+    auto get_row = [&](const unsigned char *rbuf, int kgl, int i, int g) -> typename F::row {
+        if constexpr (C::RES) {
+            return lds_row<PREC>(s_row, (size_t)g * S::NRB + rbl[i], lane);
+        } else {
+            const int frag = kgl * S::TRB + wm * C::WM + i;
+            const unsigned char *p = rbuf + (size_t)(frag * 64 + lane) * S::RPART * 16;
+            if constexpr (PREC == PREC_F64) return *reinterpret_cast<const f64x4 *>(p);
+            else if constexpr (PREC == PREC_F32) return *reinterpret_cast<const f32x4 *>(p);
+            else if constexpr (PREC == PREC_BF16) return *reinterpret_cast<const bf16x8 *>(p);
+            else if constexpr (PREC == PREC_SPLIT_BF16) {
+                SplitBF r;
+                r.hi = *reinterpret_cast<const bf16x8 *>(p);
+                r.lo = *reinterpret_cast<const bf16x8 *>(p + 16);
+                return r;
+            } else {
+                SplitH r;
+                r.hi = *reinterpret_cast<const f16x8 *>(p);
+                r.lo = *reinterpret_cast<const f16x8 *>(p + 16);
+                return r;
+            }
+        }
+    };
+    auto multiply = [&](const typename F::row (&r)[C::WM], const unsigned char *buf, int kgl) {
+        typename F::col cf[C::WN];
+#pragma unroll
+        for (int j = 0; j < C::WN; ++j) cf[j] = get_col<PREC, S>(buf, kgl, cbt0 + j, lane);
 #pragma unroll
         for (int i = 0; i < C::WM; ++i)
-            if (row_ok[i]) ra[i] = load_row<PREC>(a, (size_t)g * S::NRB + rb0 + i, lane);
 #pragma unroll
-        for (int j = 0; j < C::WN; ++j) {
-            if (cb0 + j >= S::NCB) continue;
-            DT vals[S::SLOTS];
-#pragma unroll
-            for (int pp = 0; pp < S::PPL; ++pp) {
-                const int q = g * S::KGP + half * S::PPL + pp;
-                const int qc = q < NQ ? q : 0;
-                const int q1 = qc % N, q2 = (qc / N) % N, q3 = qc / (N * N);
-                const DT *Dh = s_D + ((size_t)col_el[j] * NQP + q) * S::DSTR;
-                DT dloc[13];
-#pragma unroll
-                for (int u = 0; u < 13; ++u) dloc[u] = Dh[u];
-                const DT la = ld[(q1 * N + col_a[j]) * 2], da = ld[(q1 * N + col_a[j]) * 2 + 1];
-                const DT lb = ld[(q2 * N + col_b[j]) * 2], db = ld[(q2 * N + col_b[j]) * 2 + 1];
-                const DT lc = ld[(q3 * N + col_c[j]) * 2], dc = ld[(q3 * N + col_c[j]) * 2 + 1];
-                DT out[4];
-                column_values<DT>(dloc, la, da, lb, db, lc, dc, out);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) vals[pp * 4 + r] = col_ok[j] ? out[r] : DT(0);
-            }
-            const typename F::col cf = pack_col<PREC, DT>(vals);
+            for (int j = 0; j < C::WN; ++j) mma_stage<PREC, 0>(acc[i][j], r[i], cf[j]);
+        if constexpr (S::SPLIT) {
 #pragma unroll
             for (int i = 0; i < C::WM; ++i)
-                if (row_ok[i]) mma<PREC>(acc[i][j], ra[i], cf);
+#pragma unroll
+                for (int j = 0; j < C::WN; ++j) mma_stage<PREC, 1>(acc[i][j], r[i], cf[j]);
+#pragma unroll
+            for (int i = 0; i < C::WM; ++i)
+#pragma unroll
+                for (int j = 0; j < C::WN; ++j) mma_stage<PREC, 2>(acc[i][j], r[i], cf[j]);
         }
-    }
-
-    // ---- epilogue: unpadded row-major store ----
-    using OT = typename std::conditional<PREC == PREC_F64, double, float>::type;
-    OT *outA = reinterpret_cast<OT *>(a.out_A);
+    };
+    // per-wave production (PROD 1): lane's column of each of the wave's column blocks
+    int w_ab[C::WN], w_bb[C::WN], w_cb[C::WN], w_el[C::WN];
 #pragma unroll
     for (int j = 0; j < C::WN; ++j) {
-        if (!col_ok[j]) continue;
-        const int col = (cb0 + j) * TM + (lane % TM);
+        const int cbg = ct * S::TCB + cbt0 + j;
+        const int cbc = cbg < S::NCB ? cbg : S::NCB - 1;
+        const int col = cbc * TM + lane % TM;
         const int el = col / S::NSP, jj = col % S::NSP;
-        const int64_t e = element_id(elist, e0 + el);
-        const int64_t base = a.a_off ? a.a_off[e] : e * (int64_t)NS * NS;
-        const float us = s_unsc[el];
+        const bool ok = cbg < S::NCB && jj < NS && el < neg;
+        const int jc = ok ? jj : 0;
+        w_el[j] = el;
+        w_ab[j] = (jc % N + (ok ? 0 : N * N)) * (int)sizeof(DT2);
+        w_bb[j] = ((jc / N) % N) * (int)sizeof(DT2);
+        w_cb[j] = (jc / (N * N)) * (int)sizeof(DT2);
+    }
+    const int w_q0 = (lane / TM) * S::PPL;
+    auto produce_wave = [&](int g, int j) -> typename F::col {
+        DT vals[S::SLOTS];
 #pragma unroll
-        for (int i = 0; i < C::WM; ++i) {
-            if (!row_ok[i]) continue;
+        for (int sub = 0; sub < S::PPL; ++sub) {
+            const int q = g * S::KGP + w_q0 + sub;
+            const DT *Dh = s_D + ((size_t)w_el[j] * NQP + q) * S::DSTR;
+            DT dloc[13];
 #pragma unroll
-            for (int v = 0; v < F::ACC_N; ++v) {
-                const int row = (rb0 + i) * TM + acc_row<FAM>(lane, v);
-                if (row < NS) {
-                    if constexpr (PREC == PREC_F64) outA[base + (int64_t)row * NS + jj] = acc[i][j][v];
-                    else outA[base + (int64_t)row * NS + jj] = acc[i][j][v] * us;
+            for (int uu = 0; uu < 13; ++uu) dloc[uu] = Dh[uu];
+            const DT2 fa = *reinterpret_cast<const DT2 *>(ldb + s_pt[q] + w_ab[j]);
+            const DT2 fb = *reinterpret_cast<const DT2 *>(ldb + s_pt[NQP + q] + w_bb[j]);
+            const DT2 fc = *reinterpret_cast<const DT2 *>(ldb + s_pt[2 * NQP + q] + w_cb[j]);
+            DT out[4];
+            column_values<DT>(dloc, fa[0], fa[1], fb[0], fb[1], fc[0], fc[1], out);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) vals[sub * 4 + r] = out[r];
+        }
+        return pack_col<PREC, DT>(vals);
+    };
+    auto multiply_regs = [&](const typename F::row (&r)[C::WM], const typename F::col (&cf)[C::WN]) {
+#pragma unroll
+        for (int i = 0; i < C::WM; ++i)
+#pragma unroll
+            for (int j = 0; j < C::WN; ++j) mma_stage<PREC, 0>(acc[i][j], r[i], cf[j]);
+        if constexpr (S::SPLIT) {
+#pragma unroll
+            for (int i = 0; i < C::WM; ++i)
+#pragma unroll
+                for (int j = 0; j < C::WN; ++j) mma_stage<PREC, 1>(acc[i][j], r[i], cf[j]);
+#pragma unroll
+            for (int i = 0; i < C::WM; ++i)
+#pragma unroll
+                for (int j = 0; j < C::WN; ++j) mma_stage<PREC, 2>(acc[i][j], r[i], cf[j]);
+        }
+    };
+
+    auto consume_chunk = [&](int ch, const unsigned char *cbuf, const unsigned char *rbuf) {
+        if constexpr (C::PROD == 0) {
+#pragma unroll
+            for (int kgl = 0; kgl < S::KC; ++kgl) {
+                typename F::row rr[C::WM];
+#pragma unroll
+                for (int i = 0; i < C::WM; ++i) rr[i] = get_row(rbuf, kgl, i, ch * S::KC + kgl);
+                multiply(rr, cbuf, kgl);
+            }
+        } else {
+            // C of the next k-group is produced while the current one is multiplied
+            typename F::col cf[C::WN];
+#pragma unroll
+            for (int j = 0; j < C::WN; ++j) cf[j] = produce_wave(ch * S::KC, j);
+#pragma unroll
+            for (int kgl = 0; kgl < S::KC; ++kgl) {
+                const int g = ch * S::KC + kgl;
+                typename F::row rr[C::WM];
+#pragma unroll
+                for (int i = 0; i < C::WM; ++i) rr[i] = get_row(rbuf, kgl, i, g);
+                typename F::col cn[C::WN];
+                if (kgl + 1 < S::KC) {
+#pragma unroll
+                    for (int j = 0; j < C::WN; ++j) cn[j] = produce_wave(g + 1, j);
+                }
+                multiply_regs(rr, cf);
+                if (kgl + 1 < S::KC) {
+#pragma unroll
+                    for (int j = 0; j < C::WN; ++j) cf[j] = cn[j];
                 }
             }
         }
-    }
+    };
 
-    // ---- load vector (FP64), by the column-tile-0 workgroup of each row tile ----
-    if (ct == 0 && a.out_b) {
-        const int r0 = rt * S::TRB * TM;
-        const int r1 = (r0 + S::TRB * TM) < NS ? (r0 + S::TRB * TM) : NS;
-        const int rows = r1 - r0;
-        OT *outb = reinterpret_cast<OT *>(a.out_b);
+    // ---- main loop: produce chunk c+1 and fetch its rows while multiplying chunk c ----
+    fetch_rows(0);
+    store_rows(s_rb0);
+    if constexpr (C::PROD == 0) produce_chunk(0, s_cb0);
+    __syncthreads();
 #pragma unroll 1
-        for (int t = tid; t < EG * rows; t += NT) {
-            const int el = t / rows, r = r0 + t % rows;
-            if (el >= neg) continue;
-            const int ra_ = r % N, rb_ = (r / N) % N, rc_ = r / (N * N);
-            const double *wf = s_wf + (size_t)el * NQP;
+    for (int ch = 0; ch + 1 < S::NCH; ++ch) {
+        const bool odd = ch & 1;
+        fetch_rows(ch + 1);
+        // reads of the current chunk are issued before the writes of the next one, so the
+        // MFMAs do not wait behind the producer's LDS stores and the two interleave
+        consume_chunk(ch, odd ? s_cb1 : s_cb0, odd ? s_rb1 : s_rb0);
+        if constexpr (C::PROD == 0) produce_chunk(ch + 1, odd ? s_cb0 : s_cb1);
+        store_rows(odd ? s_rb0 : s_rb1);
+        if constexpr (C::PROD == 0 || !C::RES) __syncthreads();  // chunk buffers change hands
+    }
+    consume_chunk(S::NCH - 1, ((S::NCH - 1) & 1) ? s_cb1 : s_cb0, ((S::NCH - 1) & 1) ? s_rb1 : s_rb0);
+
+    using OT = typename S::OT;
+    __syncthreads();  // every wave is done with the point matrices and the chunks
+
+    // ---- load vector b_i = sum_q w_q detJ_q f phi_i(xi_q), FP64, by one workgroup per element.
+    // The sum runs over q1, q2, q3 in turn (phi_i is a product of 1-D factors); same terms, the
+    // additions grouped by direction.
+    if (rt == 0 && ct == 0 && a.out_b) {
+        const int tot = EG * NS;
+        // t1[el][q3][q2][a] = sum_q1 L[q1][a] wf[el][q1 + N q2 + N^2 q3]
+        for (int t = tid; t < tot; t += NT) {
+            const int el = t / NS, r = t % NS;
+            const int a_ = r % N, q2 = (r / N) % N, q3 = r / (N * N);
+            const double *wf = s_wf + (size_t)el * NQP + N * (q2 + N * q3);
             double sum = 0.0;
-#pragma unroll 1
-            for (int q3 = 0; q3 < N; ++q3) {
-                const double l3 = s_ld64[(q3 * N + rc_) * 2];
-#pragma unroll 1
-                for (int q2 = 0; q2 < N; ++q2) {
-                    const double l23 = l3 * s_ld64[(q2 * N + rb_) * 2];
 #pragma unroll
-                    for (int q1 = 0; q1 < N; ++q1)
-                        sum += wf[q1 + N * (q2 + N * q3)] * s_ld64[(q1 * N + ra_) * 2] * l23;
-                }
-            }
+            for (int q1 = 0; q1 < N; ++q1) sum += s_ld64[(q1 * N + a_) * 2] * wf[q1];
+            s_t1[t] = sum;
+        }
+        __syncthreads();
+        // t2[el][q3][b][a] = sum_q2 L[q2][b] t1[el][q3][q2][a]
+        for (int t = tid; t < tot; t += NT) {
+            const int el = t / NS, r = t % NS;
+            const int a_ = r % N, b_ = (r / N) % N, q3 = r / (N * N);
+            const double *t1 = s_t1 + (size_t)el * NS + N * N * q3 + a_;
+            double sum = 0.0;
+#pragma unroll
+            for (int q2 = 0; q2 < N; ++q2) sum += s_ld64[(q2 * N + b_) * 2] * t1[N * q2];
+            s_t2[t] = sum;
+        }
+        __syncthreads();
+        // b[el][c][b][a] = sum_q3 L[q3][c] t2[el][q3][b][a]
+        OT *outb = reinterpret_cast<OT *>(a.out_b);
+        for (int t = tid; t < tot; t += NT) {
+            const int el = t / NS, r = t % NS;
+            if (el >= neg) continue;
+            const int ab = r % (N * N), c_ = r / (N * N);
+            const double *t2 = s_t2 + (size_t)el * NS + ab;
+            double sum = 0.0;
+#pragma unroll
+            for (int q3 = 0; q3 < N; ++q3) sum += s_ld64[(q3 * N + c_) * 2] * t2[N * N * q3];
             const int64_t e = element_id(elist, e0 + el);
             const int64_t base = a.b_off ? a.b_off[e] : e * (int64_t)NS;
             outb[base + r] = (OT)sum;
         }
+        __syncthreads();  // the temporaries overlay the staging area below
     }
+
+    // ---- epilogue: unpadded row-major store ----
+    OT *outA = reinterpret_cast<OT *>(a.out_A);
+    if constexpr (S::STAGE_OUT) {
+        // The workgroup owns whole elements: stage [row][column] in LDS, then write each
+        // element's contiguous Ns x Ns block with aligned 16-byte stores.
+        OT *s_out = reinterpret_cast<OT *>(smem + S::off_D);
+#pragma unroll
+        for (int j = 0; j < C::WN; ++j) {
+            const int cb = ct * S::TCB + cbt0 + j;
+            if (cb >= S::NCB) continue;
+            const int col = cb * TM + (lane % TM);
+            const int el = col / S::NSP;
+            const float us = S::SPLIT ? a.row_scale_inv / split_scale(s_dmax[el], a.c_bound)
+                                      : a.row_scale_inv;
+#pragma unroll
+            for (int i = 0; i < C::WM; ++i) {
+                if (rb0 + i >= S::NRB) continue;
+#pragma unroll
+                for (int v = 0; v < F::ACC_N; ++v) {
+                    const int row = (rb0 + i) * TM + acc_row<FAM>(lane, v);
+                    if (row < NS) {
+                        if constexpr (PREC == PREC_F64) s_out[row * S::OPITCH + col] = acc[i][j][v];
+                        else s_out[row * S::OPITCH + col] = acc[i][j][v] * us;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        constexpr int VW = 16 / sizeof(OT);
+        for (int el = 0; el < neg; ++el) {
+            const int64_t e = element_id(elist, e0 + el);
+            OT *dst = outA + (a.a_off ? a.a_off[e] : e * (int64_t)NS * NS);
+            const OT *src = s_out + el * S::NSP;
+            const int mis = (int)((reinterpret_cast<uintptr_t>(dst) & 15) / sizeof(OT));
+            const int head = mis ? (VW - mis < NS * NS ? VW - mis : NS * NS) : 0;
+            const int nvec = (NS * NS - head) / VW;
+            const int tail0 = head + nvec * VW;
+            if (tid < head) dst[tid] = src[(tid / NS) * S::OPITCH + tid % NS];
+            for (int k = tid; k < nvec; k += NT) {
+                const int idx = head + k * VW;
+                typedef OT vec_t __attribute__((ext_vector_type(VW)));
+                vec_t vv;
+#pragma unroll
+                for (int u = 0; u < VW; ++u) {
+                    const int x = idx + u;
+                    vv[u] = src[(x / NS) * S::OPITCH + x % NS];
+                }
+                *reinterpret_cast<vec_t *>(dst + idx) = vv;
+            }
+            for (int x = tail0 + tid; x < NS * NS; x += NT) dst[x] = src[(x / NS) * S::OPITCH + x % NS];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < C::WN; ++j) {
+            const int cb = ct * S::TCB + cbt0 + j;
+            if (cb >= S::NCB) continue;
+            const int col = cb * TM + (lane % TM);
+            const int el = col / S::NSP, jj = col % S::NSP;
+            if (jj >= NS || el >= neg) continue;
+            const int64_t e = element_id(elist, e0 + el);
+            const int64_t base = a.a_off ? a.a_off[e] : e * (int64_t)NS * NS;
+            const float us = S::SPLIT ? a.row_scale_inv / split_scale(s_dmax[el], a.c_bound)
+                                      : a.row_scale_inv;
+#pragma unroll
+            for (int i = 0; i < C::WM; ++i) {
+                if (rb0 + i >= S::NRB) continue;
+#pragma unroll
+                for (int v = 0; v < F::ACC_N; ++v) {
+                    const int row = (rb0 + i) * TM + acc_row<FAM>(lane, v);
+                    if (row < NS) {
+                        if constexpr (PREC == PREC_F64) outA[base + (int64_t)row * NS + jj] = acc[i][j][v];
+                        else outA[base + (int64_t)row * NS + jj] = acc[i][j][v] * us;
+                    }
+                }
+            }
+        }
+    }
+
+    __syncthreads();  // LDS is rewritten by the next item
 }
 
-// Grid-stride loop over work items; the element count comes from the host (nel) or, for the
-// buckets of a mixed-degree call, from device memory (seg), so no host synchronisation is
-// needed between bucketing and integration.
+// Persistent kernel: a grid-stride loop over work items. The element count comes from the host
+// (nel) or, for the buckets of a mixed-degree call, from device memory (seg), so no host
+// synchronisation is needed between bucketing and integration.
 template <int P, int PREC, class C>
 __global__ void __launch_bounds__(C::NW * 64) __attribute__((amdgpu_waves_per_eu(C::OCC, 8)))
 k_integrate(const KArgs a)
 {
     using S = Shape<P, PREC, C>;
+    constexpr int N = S::N, NT = S::NT;
     extern __shared__ __align__(16) unsigned char smem[];
     int64_t nel = a.nel;
     const int32_t *elist = a.elist;
@@ -642,9 +1160,71 @@ k_integrate(const KArgs a)
         nel = a.seg[1];
     }
     const int64_t total = ((nel + S::EG - 1) / S::EG) * S::RT * S::CT;
-    for (int64_t wi = blockIdx.x; wi < total; wi += gridDim.x) {
-        integrate_item<P, PREC, C>(a, wi, nel, elist, smem);
-        __syncthreads();
+    if ((int64_t)blockIdx.x >= total) return;
+    const int tid = threadIdx.x;
+    const int reclen = a.mode == 0 ? 14 : 10;
+
+    // ---- per-workgroup constants: tables, field descriptor, point rows, resident row table ----
+    double *s_fld = reinterpret_cast<double *>(smem + S::off_fld);
+    double *s_ld64 = reinterpret_cast<double *>(smem + S::off_ld64);
+    float *s_ld32 = reinterpret_cast<float *>(smem + S::off_ld32);
+    double *s_qw = reinterpret_cast<double *>(smem + S::off_qw);
+    int *s_pt = reinterpret_cast<int *>(smem + S::off_pt);
+    if (a.mode == 1)
+        for (int t = tid; t < 175; t += NT) s_fld[t] = a.field[t];
+    for (int t = tid; t < N * N * 2; t += NT) {
+        s_ld64[t] = a.LD64[t];
+        s_ld32[t] = a.LD32[t];
+        s_ld64[N * N * 2 + t] = 0.0;
+        s_ld32[N * N * 2 + t] = 0.0f;
+    }
+    for (int t = tid; t < N; t += NT) {
+        s_qw[t] = a.xq[t];
+        s_qw[N + t] = a.wq[t];
+    }
+    // per point: byte offsets of the 1-D table rows it reads (q1, q2, q3), three arrays
+    {
+        constexpr int ROWBYTES = N * 2 * sizeof(typename S::DT);
+        for (int q = tid; q < S::NQP; q += NT) {
+            const bool ok = q < S::NQ;
+            s_pt[q] = ok ? (q % N) * ROWBYTES : 0;
+            s_pt[S::NQP + q] = ok ? ((q / N) % N) * ROWBYTES : 0;
+            s_pt[2 * S::NQP + q] = ok ? (q / (N * N)) * ROWBYTES : 0;
+        }
+    }
+    if constexpr (C::RES) {
+        // [frag][part][lane] x 16 B (split), [frag][lane] x 16 B or 32 B otherwise
+        typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+        u32x4 *dst = reinterpret_cast<u32x4 *>(smem + S::off_row);
+        const u32x4 *hi = reinterpret_cast<const u32x4 *>(a.row_hi);
+        const u32x4 *lo = reinterpret_cast<const u32x4 *>(a.row_lo);
+        constexpr size_t nfrag = size_t(S::NGP) * S::NRB;
+        if constexpr (S::SPLIT) {
+            for (size_t t = tid; t < nfrag * 128; t += NT) {
+                const size_t frag = t / 128, part = (t / 64) % 2, l = t % 64;
+                dst[t] = part ? lo[frag * 64 + l] : hi[frag * 64 + l];
+            }
+        } else {
+            constexpr int per = S::ROWB / 16;
+            for (size_t t = tid; t < nfrag * 64 * per; t += NT) dst[t] = hi[t];
+        }
+    }
+
+    int64_t wi = blockIdx.x;
+    Item it = decode_item<S>(wi, nel);
+    double pf[S::PFN], pf_next[S::PFN];
+    fetch_elements<S>(a, elist, it, reclen, pf);
+    __syncthreads();
+    for (;;) {
+        const int64_t wn = wi + gridDim.x;
+        const bool has_next = wn < total;
+        const Item itn = has_next ? decode_item<S>(wn, nel) : it;
+        integrate_item<P, PREC, C>(a, it, elist, reclen, smem, pf, pf_next, has_next, itn);
+        if (!has_next) break;
+        wi = wn;
+        it = itn;
+#pragma unroll
+        for (int k = 0; k < S::PFN; ++k) pf[k] = pf_next[k];
     }
 }
 

@@ -1,80 +1,156 @@
-// fem_launch.h -- tile configurations per (degree, precision) and the launch of one degree.
+// fem_launch.h -- the compiled tile configurations ("variants") per (degree, precision family)
+// and their launch. Variant 0 is the default; fem_autotune times all variants of a
+// (degree, precision) and records the fastest.
 #pragma once
 #include "fem_kernel.h"
 
 namespace fem {
 
-// Work-item shapes. TM = 32 families (FP32, BF16, split): p = 1 packs 16 elements of 8 trial
-// functions into 4 column blocks; p = 2, 3 put 4 and 2 elements side by side; p >= 4 tile one
-// element. FP64 (TM = 16) uses the same scheme with 16-wide blocks.
-template <int P, int FAM> struct DefaultCfg;
-template <> struct DefaultCfg<1, MF_K16> { using type = Cfg<16, 1, 4, 1, 1, 2>; };
-template <> struct DefaultCfg<2, MF_K16> { using type = Cfg<4, 1, 4, 1, 1, 2>; };
-template <> struct DefaultCfg<3, MF_K16> { using type = Cfg<2, 1, 4, 2, 1, 2>; };
-template <> struct DefaultCfg<4, MF_K16> { using type = Cfg<1, 1, 4, 4, 1, 2>; };
-template <> struct DefaultCfg<5, MF_K16> { using type = Cfg<1, 1, 4, 4, 1, 1>; };
-template <> struct DefaultCfg<6, MF_K16> { using type = Cfg<1, 1, 4, 6, 1>; };
-template <> struct DefaultCfg<7, MF_K16> { using type = Cfg<1, 1, 4, 8, 1>; };
-template <int P> struct DefaultCfg<P, MF_F32> { using type = typename DefaultCfg<P, MF_K16>::type; };
-template <> struct DefaultCfg<1, MF_F64> { using type = Cfg<8, 1, 4, 1, 1, 2>; };
-template <> struct DefaultCfg<2, MF_F64> { using type = Cfg<2, 1, 4, 2, 1, 2>; };
-template <> struct DefaultCfg<3, MF_F64> { using type = Cfg<1, 1, 4, 4, 1, 2>; };
-template <> struct DefaultCfg<4, MF_F64> { using type = Cfg<1, 1, 4, 8, 1>; };
-template <> struct DefaultCfg<5, MF_F64> { using type = Cfg<1, 1, 4, 7, 1>; };
-template <> struct DefaultCfg<6, MF_F64> { using type = Cfg<1, 1, 4, 8, 1>; };
-template <> struct DefaultCfg<7, MF_F64> { using type = Cfg<1, 1, 4, 8, 1>; };
+constexpr int MAX_VARIANTS = 3;
 
-template <int P, int PREC>
+// Cfg<EG, WGM, WGN, WM, WN, OCC, KC, RES, PROD> (see fem_kernel.h). For the 32-wide families
+// (FP32, BF16, split): p = 1 packs 16 elements of 8 trial functions into 4 column blocks;
+// p = 2, 3 put 4 (8) and 2 (4) elements side by side; p = 4 gives one (two) elements to a
+// workgroup; p >= 5 tile one element into row x column tiles. FP64 uses 16-wide blocks.
+template <int P, int FAM, int V> struct VariantCfg { using type = void; };
+
+// -- 32-wide families --
+template <> struct VariantCfg<1, MF_K16, 0> { using type = Cfg<16, 1, 4, 1, 1, 2, 2, 1, 0>; };
+template <> struct VariantCfg<1, MF_K16, 1> { using type = Cfg<16, 1, 4, 1, 1, 3, 2, 1, 1>; };
+template <> struct VariantCfg<2, MF_K16, 0> { using type = Cfg<4, 1, 4, 1, 1, 3, 2, 1, 1>; };
+template <> struct VariantCfg<2, MF_K16, 1> { using type = Cfg<8, 1, 4, 1, 2, 2, 2, 1, 1>; };
+template <> struct VariantCfg<2, MF_K16, 2> { using type = Cfg<4, 1, 4, 1, 1, 2, 2, 1, 0>; };
+template <> struct VariantCfg<3, MF_K16, 0> { using type = Cfg<2, 1, 4, 2, 1, 2, 2, 0, 1>; };
+template <> struct VariantCfg<3, MF_K16, 1> { using type = Cfg<4, 1, 4, 2, 2, 2, 2, 1, 1>; };
+template <> struct VariantCfg<3, MF_K16, 2> { using type = Cfg<2, 1, 4, 2, 1, 2, 2, 0, 0>; };
+template <> struct VariantCfg<4, MF_K16, 0> { using type = Cfg<1, 1, 4, 4, 1, 2, 2, 0, 1>; };
+template <> struct VariantCfg<4, MF_K16, 1> { using type = Cfg<1, 1, 4, 4, 1, 2, 4, 0, 1>; };
+template <> struct VariantCfg<4, MF_K16, 2> { using type = Cfg<1, 1, 4, 4, 1, 2, 2, 0, 0>; };
+template <> struct VariantCfg<5, MF_K16, 0> { using type = Cfg<1, 1, 4, 4, 1, 1, 2, 0, 0>; };
+template <> struct VariantCfg<5, MF_K16, 1> { using type = Cfg<1, 1, 4, 4, 1, 1, 2, 0, 1>; };
+template <> struct VariantCfg<6, MF_K16, 0> { using type = Cfg<1, 1, 4, 6, 1, 1, 2, 0, 0>; };
+template <> struct VariantCfg<6, MF_K16, 1> { using type = Cfg<1, 1, 4, 6, 1, 1, 2, 0, 1>; };
+template <> struct VariantCfg<7, MF_K16, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 2, 0, 0>; };
+template <> struct VariantCfg<7, MF_K16, 1> { using type = Cfg<1, 1, 4, 8, 1, 1, 2, 0, 1>; };
+template <int P, int V> struct VariantCfg<P, MF_F32, V> { using type = typename VariantCfg<P, MF_K16, V>::type; };
+// -- FP64 (16-wide blocks) --
+template <> struct VariantCfg<1, MF_F64, 0> { using type = Cfg<8, 1, 4, 1, 1, 2, 2, 1, 0>; };
+template <> struct VariantCfg<2, MF_F64, 0> { using type = Cfg<2, 1, 4, 2, 1, 2, 2, 0, 0>; };
+template <> struct VariantCfg<3, MF_F64, 0> { using type = Cfg<1, 1, 4, 4, 1, 2, 2, 0, 0>; };
+template <> struct VariantCfg<4, MF_F64, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 1, 0, 0>; };
+template <> struct VariantCfg<5, MF_F64, 0> { using type = Cfg<1, 1, 4, 7, 1, 1, 1, 0, 0>; };
+template <> struct VariantCfg<6, MF_F64, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 1, 0, 0>; };
+template <> struct VariantCfg<7, MF_F64, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 1, 0, 0>; };
+
+template <int P, int PREC, int V>
 struct Inst {
-    using C = typename DefaultCfg<P, family_of(PREC)>::type;
+    using C = typename VariantCfg<P, family_of(PREC), V>::type;
     using S = Shape<P, PREC, C>;
-    static void *fn() { return reinterpret_cast<void *>(&k_integrate<P, PREC, C>); }
+    static inline int resident_per_cu = 1;  // workgroups of this instance one CU holds at once
+    static const void *fn() { return reinterpret_cast<const void *>(&k_integrate<P, PREC, C>); }
     static hipError_t prepare()
     {
+        hipError_t e = hipSuccess;
         if (S::lds_bytes > 65536)
-            return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_integrate<P, PREC, C>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::lds_bytes);
+            e = hipFuncSetAttribute(fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::lds_bytes);
+        if (e != hipSuccess) return e;
+        int blocks = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn(), S::NT, S::lds_bytes);
+        if (e != hipSuccess) return e;
+        resident_per_cu = blocks > 0 ? blocks : 1;
         return hipSuccess;
     }
-    // a.nel is the exact element count, or an upper bound when a.seg supplies the count.
-    static hipError_t launch(const KArgs &a, hipStream_t s, int64_t grid_cap)
+    // a.nel is the exact element count, or an upper bound when a.seg supplies the count. The
+    // grid is persistent: at most the workgroups the device holds at once.
+    static hipError_t launch(const KArgs &a, hipStream_t s, int cus)
     {
         const int64_t groups = (a.nel + S::EG - 1) / S::EG;
         const int64_t total = groups * S::RT * S::CT;
-        const int64_t grid = total < grid_cap ? total : grid_cap;
+        const int64_t cap = int64_t(cus) * resident_per_cu;
+        const int64_t grid = total < cap ? total : cap;
         if (grid <= 0) return hipSuccess;
-        if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_integrate<P, PREC, C>), dim3((unsigned)grid), dim3(S::NT), S::lds_bytes, s, a);
         return hipGetLastError();
     }
 };
 
+// Per-variant helpers that tolerate variants a family does not define.
+template <int P, int PREC, int V>
+constexpr bool has_variant() { return !std::is_void<typename VariantCfg<P, family_of(PREC), V>::type>::value; }
+
+template <int P, int PREC, int V>
+hipError_t prepare_variant()
+{
+    if constexpr (has_variant<P, PREC, V>()) return Inst<P, PREC, V>::prepare();
+    else return hipSuccess;
+}
+
+template <int P, int PREC, int V>
+hipError_t launch_variant(const KArgs &a, hipStream_t s, int cus)
+{
+    if constexpr (has_variant<P, PREC, V>()) return Inst<P, PREC, V>::launch(a, s, cus);
+    else return hipErrorInvalidValue;
+}
+
+template <int P, int PREC>
+int count_variants()
+{
+    return has_variant<P, PREC, 0>() + has_variant<P, PREC, 1>() + has_variant<P, PREC, 2>();
+}
 
 template <int PREC>
 hipError_t prepare_all()
 {
-    hipError_t e;
-    if ((e = Inst<1, PREC>::prepare()) != hipSuccess) return e;
-    if ((e = Inst<2, PREC>::prepare()) != hipSuccess) return e;
-    if ((e = Inst<3, PREC>::prepare()) != hipSuccess) return e;
-    if ((e = Inst<4, PREC>::prepare()) != hipSuccess) return e;
-    if ((e = Inst<5, PREC>::prepare()) != hipSuccess) return e;
-    if ((e = Inst<6, PREC>::prepare()) != hipSuccess) return e;
-    return Inst<7, PREC>::prepare();
+    hipError_t e = hipSuccess;
+    auto one = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+    one(prepare_variant<1, PREC, 0>()); one(prepare_variant<1, PREC, 1>()); one(prepare_variant<1, PREC, 2>());
+    one(prepare_variant<2, PREC, 0>()); one(prepare_variant<2, PREC, 1>()); one(prepare_variant<2, PREC, 2>());
+    one(prepare_variant<3, PREC, 0>()); one(prepare_variant<3, PREC, 1>()); one(prepare_variant<3, PREC, 2>());
+    one(prepare_variant<4, PREC, 0>()); one(prepare_variant<4, PREC, 1>()); one(prepare_variant<4, PREC, 2>());
+    one(prepare_variant<5, PREC, 0>()); one(prepare_variant<5, PREC, 1>()); one(prepare_variant<5, PREC, 2>());
+    one(prepare_variant<6, PREC, 0>()); one(prepare_variant<6, PREC, 1>()); one(prepare_variant<6, PREC, 2>());
+    one(prepare_variant<7, PREC, 0>()); one(prepare_variant<7, PREC, 1>()); one(prepare_variant<7, PREC, 2>());
+    return e;
+}
+
+template <int P, int PREC>
+hipError_t launch_pv(int v, const KArgs &a, hipStream_t s, int cus)
+{
+    switch (v) {
+    case 0: return launch_variant<P, PREC, 0>(a, s, cus);
+    case 1: return launch_variant<P, PREC, 1>(a, s, cus);
+    case 2: return launch_variant<P, PREC, 2>(a, s, cus);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <int PREC>
-hipError_t launch_p(int p, const KArgs &a, hipStream_t s, int64_t cap)
+hipError_t launch_p(int p, int v, const KArgs &a, hipStream_t s, int64_t cus)
 {
     switch (p) {
-    case 1: return Inst<1, PREC>::launch(a, s, cap);
-    case 2: return Inst<2, PREC>::launch(a, s, cap);
-    case 3: return Inst<3, PREC>::launch(a, s, cap);
-    case 4: return Inst<4, PREC>::launch(a, s, cap);
-    case 5: return Inst<5, PREC>::launch(a, s, cap);
-    case 6: return Inst<6, PREC>::launch(a, s, cap);
-    case 7: return Inst<7, PREC>::launch(a, s, cap);
+    case 1: return launch_pv<1, PREC>(v, a, s, (int)cus);
+    case 2: return launch_pv<2, PREC>(v, a, s, (int)cus);
+    case 3: return launch_pv<3, PREC>(v, a, s, (int)cus);
+    case 4: return launch_pv<4, PREC>(v, a, s, (int)cus);
+    case 5: return launch_pv<5, PREC>(v, a, s, (int)cus);
+    case 6: return launch_pv<6, PREC>(v, a, s, (int)cus);
+    case 7: return launch_pv<7, PREC>(v, a, s, (int)cus);
     default: return hipErrorInvalidValue;
+    }
+}
+
+template <int PREC>
+int variants_p(int p)
+{
+    switch (p) {
+    case 1: return count_variants<1, PREC>();
+    case 2: return count_variants<2, PREC>();
+    case 3: return count_variants<3, PREC>();
+    case 4: return count_variants<4, PREC>();
+    case 5: return count_variants<5, PREC>();
+    case 6: return count_variants<6, PREC>();
+    case 7: return count_variants<7, PREC>();
+    default: return 0;
     }
 }
 

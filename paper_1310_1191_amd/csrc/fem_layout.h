@@ -40,6 +40,9 @@ FEM_HD constexpr int fam_slots(int fam) { return fam == MF_K16 ? 8 : 4; }
 
 FEM_HD constexpr int ns_of(int p) { return (p + 1) * (p + 1) * (p + 1); }
 FEM_HD constexpr int groups_of(int p, int fam) { return (ns_of(p) + fam_kgp(fam) - 1) / fam_kgp(fam); }
+// Row-operand tables hold this many k-groups (a multiple of 8, so that every chunk size of the
+// kernels divides it); groups past groups_of() are zero.
+FEM_HD constexpr int groups_padded(int p, int fam) { return (groups_of(p, fam) + 7) / 8 * 8; }
 FEM_HD constexpr int rblocks_of(int p, int fam) { return (ns_of(p) + fam_tm(fam) - 1) / fam_tm(fam); }
 
 // Point and component addressed by (group g, lane l, slot v).

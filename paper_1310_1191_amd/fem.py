@@ -73,13 +73,22 @@ def load():
     lib.fem_abi_version.argtypes = []
     dp = ctypes.POINTER(ctypes.c_double)
     lib.fem_reference_tables.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp]
+    lib.fem_field_advance.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
+    lib.fem_variant_count.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.fem_get_variant.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.fem_set_variant.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.fem_autotune.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_char_p,
+                                 ctypes.POINTER(ctypes.c_int), dp]
+    lib.fem_load_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]
     _lib = lib
     return lib
 
 
 def exported_symbols():
     return ["fem_init", "fem_finalize", "fem_integrate", "fem_workspace_bytes",
-            "fem_mixed_offsets", "fem_reference_tables", "fem_strerror", "fem_abi_version"]
+            "fem_mixed_offsets", "fem_field_advance", "fem_reference_tables", "fem_strerror",
+            "fem_abi_version", "fem_variant_count", "fem_get_variant", "fem_set_variant",
+            "fem_autotune", "fem_load_tuning"]
 
 
 # ---------------------------------------------------------------------------------------------
@@ -133,6 +142,53 @@ def fem_mixed_offsets(nel: int, degree: int, a_off: int, b_off: int, workspace: 
                       workspace_bytes: int, stream: int | None) -> int:
     return int(load().fem_mixed_offsets(int(nel), degree, a_off, b_off, workspace,
                                          int(workspace_bytes), stream))
+
+
+def fem_field_advance(field: int, deltas: int, nsteps: int, step: int, stream: int | None) -> int:
+    return int(load().fem_field_advance(field, deltas, int(nsteps), step, stream))
+
+
+MAX_VARIANTS = 3
+
+
+def fem_variant_count(p: int, precision: int) -> int:
+    rc = int(load().fem_variant_count(int(p), int(precision)))
+    if rc < 0:
+        raise FemError(rc, "fem_variant_count")
+    return rc
+
+
+def fem_get_variant(p: int, precision: int) -> int:
+    rc = int(load().fem_get_variant(int(p), int(precision)))
+    if rc < 0:
+        raise FemError(rc, "fem_get_variant")
+    return rc
+
+
+def fem_set_variant(p: int, precision: int, variant: int) -> None:
+    rc = int(load().fem_set_variant(int(p), int(precision), int(variant)))
+    if rc != FEM_OK:
+        raise FemError(rc, "fem_set_variant")
+
+
+def fem_autotune(p: int, precision: int, nel: int, json_path: str | None = None):
+    """Time every variant of (p, precision) on nel synthetic elements and choose the fastest.
+    Returns (chosen variant, [ms per launch of each variant])."""
+    chosen = ctypes.c_int(-1)
+    times = (ctypes.c_double * MAX_VARIANTS)()
+    path = None if json_path is None else os.fsencode(json_path)
+    rc = int(load().fem_autotune(int(p), int(precision), int(nel), path, ctypes.byref(chosen), times))
+    if rc != FEM_OK:
+        raise FemError(rc, "fem_autotune")
+    return chosen.value, list(times)[:fem_variant_count(p, precision)]
+
+
+def fem_load_tuning(json_path: str) -> int:
+    applied = ctypes.c_int(0)
+    rc = int(load().fem_load_tuning(os.fsencode(json_path), ctypes.byref(applied)))
+    if rc != FEM_OK:
+        raise FemError(rc, "fem_load_tuning")
+    return applied.value
 
 
 # ---------------------------------------------------------------------------------------------
@@ -235,19 +291,28 @@ def integrate_mixed(geom, elem, degree, precision="split_bf16", mode: int = ELEM
         workspace = torch.empty(fem_workspace_bytes(nel), dtype=torch.uint8, device=geom.device)
     if a_off is None or b_off is None:
         a_off, b_off = mixed_offsets(degree, workspace=workspace, stream=stream)
-        total_a = int(a_off[-1].item())
-        total_b = int(b_off[-1].item())
-    else:
-        total_a = int(a_off[-1].item())
-        total_b = int(b_off[-1].item())
     dt = out_dtype(precision)
+    # output sizes are read back only when the outputs are allocated here; with caller-provided
+    # outputs the call enqueues work and never synchronises (stream capture is possible)
     if out_A is None:
-        out_A = torch.empty(total_a, dtype=dt, device=geom.device)
+        out_A = torch.empty(int(a_off[-1].item()), dtype=dt, device=geom.device)
     if out_b is None and with_b:
-        out_b = torch.empty(total_b, dtype=dt, device=geom.device)
+        out_b = torch.empty(int(b_off[-1].item()), dtype=dt, device=geom.device)
     c = make_coeffs(precision, mode, elem, field=field, degree=degree, a_off=a_off, b_off=b_off,
                     status=status, workspace=workspace)
     rc = fem_integrate(nel, 0, _ptr(geom), c, _ptr(out_A), _ptr(out_b), _stream(stream))
     if rc != FEM_OK:
         raise FemError(rc, "fem_integrate")
     return out_A, out_b, a_off, b_off
+
+
+def field_advance(field, deltas, step, stream=None):
+    """One device-side phase step of a FIELD descriptor (see fem_field_advance)."""
+    torch = _torch()
+    _check(field, torch.float64, "field")
+    _check(deltas, torch.float64, "deltas")
+    _check(step, torch.int32, "step")
+    nsteps = deltas.shape[0]
+    rc = fem_field_advance(_ptr(field), _ptr(deltas), nsteps, _ptr(step), _stream(stream))
+    if rc != FEM_OK:
+        raise FemError(rc, "fem_field_advance")

@@ -88,3 +88,22 @@ def test_reference_tables_reject_bad_degree():
     from paper_1310_1191_amd import fem
     with pytest.raises(fem.FemError):
         fem.fem_reference_tables(8)
+
+
+def test_variant_table_host_calls(lib):
+    """Variant counts and choices are host state: they need neither fem_init nor a GPU."""
+    from paper_1310_1191_amd import fem
+    for p in range(1, 8):
+        for prec in range(5):
+            n = fem.fem_variant_count(p, prec)
+            assert 1 <= n <= fem.MAX_VARIANTS
+            assert fem.fem_get_variant(p, prec) == 0
+            fem.fem_set_variant(p, prec, n - 1)
+            assert fem.fem_get_variant(p, prec) == n - 1
+            fem.fem_set_variant(p, prec, 0)
+            assert lib.fem_set_variant(p, prec, n) == fem.FEM_ECONFIG
+    assert lib.fem_variant_count(0, 0) == fem.FEM_EDEGREE
+    assert lib.fem_variant_count(3, 5) == fem.FEM_EINVAL
+    assert lib.fem_set_variant(8, 0, 0) == fem.FEM_EDEGREE
+    assert lib.fem_autotune(3, 0, 100, None, None, None) == fem.FEM_ENOTINIT
+    assert lib.fem_load_tuning(b"/nonexistent.json", None) == fem.FEM_ENOTINIT

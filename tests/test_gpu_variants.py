@@ -1,0 +1,81 @@
+"""Every compiled kernel variant (tile configuration) of every (degree, precision) against the
+FP64 oracle, and the per-degree autotuner with its tuning file. Calls go through the C ABI."""
+import json
+
+import numpy as np
+import pytest
+
+from gpu_cases import TOL_A, TOL_B, log, oracle_uniform, rel_fro, rel_vec, to_dev
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp64", "fp32", "split_bf16", "split_fp16", "bf16"]
+
+
+@pytest.fixture(scope="module")
+def fem():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    from paper_1310_1191_amd import fem as F
+    F.fem_init(0)
+    yield F
+    for p in range(1, 8):
+        for prec in PRECS:
+            F.fem_set_variant(p, F.PRECISIONS[prec], 0)
+
+
+@pytest.mark.parametrize("p", range(1, 8))
+@pytest.mark.parametrize("prec", PRECS)
+def test_every_variant_parity(fem, p, prec):
+    import torch
+    code = fem.PRECISIONS[prec]
+    n = fem.fem_variant_count(p, code)
+    assert 1 <= n <= fem.MAX_VARIANTS
+    geom, coef, A_ref, b_ref, _ = oracle_uniform(p)
+    g, c = to_dev(geom, coef)
+    first = None
+    for v in range(n):
+        fem.fem_set_variant(p, code, v)
+        assert fem.fem_get_variant(p, code) == v
+        status = torch.zeros(2, dtype=torch.int32, device="cuda")
+        A, b = fem.integrate(g, c, p, precision=prec, status=status)
+        torch.cuda.synchronize()
+        An, bn = A.double().cpu().numpy(), b.double().cpu().numpy()
+        ea, eb = rel_fro(An, A_ref), rel_vec(bn, b_ref)
+        log(f"[variant] p={p} prec={prec} v={v} errA max={ea.max():.3e} errb max={eb.max():.3e}")
+        assert status.cpu().tolist() == [0, 0]
+        assert ea.max() <= TOL_A[prec] and eb.max() <= TOL_B[prec]
+        if first is None:
+            first = bn
+        else:  # the load vector does not depend on the tile configuration
+            np.testing.assert_array_equal(bn, first)
+    fem.fem_set_variant(p, code, 0)
+
+
+def test_set_variant_rejects_missing_variant(fem):
+    for p in range(1, 8):
+        n = fem.fem_variant_count(p, fem.FP64)
+        with pytest.raises(fem.FemError):
+            fem.fem_set_variant(p, fem.FP64, n)
+
+
+def test_autotune_writes_and_reloads_choice(fem, tmp_path):
+    path = tmp_path / "tuning.json"
+    seen = {}
+    for p, prec in [(2, fem.SPLIT_FP16), (4, fem.SPLIT_FP16), (3, fem.FP64)]:
+        v, times = fem.fem_autotune(p, prec, 3000, str(path))
+        log(f"[autotune] p={p} prec={prec} chosen={v} ms={times}")
+        assert 0 <= v < fem.fem_variant_count(p, prec)
+        assert len(times) == fem.fem_variant_count(p, prec) and min(times) > 0
+        assert times[v] == min(times)
+        assert fem.fem_get_variant(p, prec) == v
+        seen[(p, prec)] = v
+    doc = json.loads(path.read_text())
+    got = {(e["p"], e["precision"]): e["variant"] for e in doc["entries"]}
+    assert got == seen
+    for (p, prec) in seen:
+        fem.fem_set_variant(p, prec, 0)
+    assert fem.fem_load_tuning(str(path)) == len(seen)
+    for (p, prec), v in seen.items():
+        assert fem.fem_get_variant(p, prec) == v
+        fem.fem_set_variant(p, prec, 0)
