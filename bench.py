@@ -53,6 +53,34 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ["fem_kernel.h", "fem_launch.h", "fem_layout.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1310_1191_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(p: int, precision: str, variant: int):
+    """HBM bytes per launch of the dominant kernel from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by what the counter reads for a copy of known size),
+    or None when there is no summary for this kernel or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"k_integrate_p{p}_{precision}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("traffic-record: "):
+            rec = json.loads(line[len("traffic-record: "):])
+    if not rec or rec.get("sources") != kernel_source_hash() or rec.get("variant") != variant:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def cpu_baseline(meshes, budget_s: float = 12.0):
     """The FP64 oracle on the host cores, timed on a bounded sample of the same workload."""
     import oracle
@@ -87,6 +115,9 @@ def main():
     ap.add_argument("--precision", default="split_fp16")
     ap.add_argument("--compare", default="fp32", help="second path timed for comparison ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run a plain elementwise copy y = -x of MIB MiB three times (the "
+                         "known-size kernel that calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the integration shards "
@@ -100,6 +131,17 @@ def main():
     assert torch.cuda.is_available(), "no GPU visible"
     dev = torch.device("cuda:0")
     fem.fem_init(0)
+
+    if args.copy_probe > 0:
+        n = args.copy_probe * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: 3 x (read {n * 4} B + write {n * 4} B)")
+        del x, y
+        torch.cuda.empty_cache()
 
     t0 = time.time()
     meshes = []
@@ -187,9 +229,10 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(ach_bytes, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach_bytes / HBM_PEAK_GBS, 4)}
-    roof["kernel"] = f"k_integrate p={pd} {args.precision}"
+    variant = fem.fem_get_variant(pd, fem.PRECISIONS[args.precision])
+    roof["kernel"] = f"k_integrate p={pd} {args.precision} variant {variant}"
     roof["launch_ms"] = round(per_p[pd], 4)
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(pd, args.precision, variant)
 
     compare = None
     if args.compare:
