@@ -146,11 +146,16 @@ int fem_reference_tables(int p, double *gauss_x, double *gauss_w, double *lobatt
  * whether the column operand C = D_q B is produced cooperatively in LDS or per wave in
  * registers, whether the B^T table stays resident in LDS). Which one is fastest depends on p,
  * the precision and the device; section 4 motivates choosing the work assignment per degree.
- * fem_integrate launches the variant chosen for its (p, precision): 0 until one of the calls
- * below chooses another. The choice is process-wide and not thread-safe. */
-#define FEM_MAX_VARIANTS 3
+ * fem_integrate launches the variant chosen for its (p, precision): a default measured on
+ * MI355X until one of the calls below chooses another. The choice is process-wide and not
+ * thread-safe.
+ * p = 0 addresses the mixed-degree path (fem_integrate with p == 0), which has two variants:
+ * 0 integrates every degree in one persistent launch (the work items of all degrees form one
+ * index space, heaviest degree first, each degree with a fixed tile configuration); 1 (the
+ * default) issues one launch per degree, each with the variant chosen for that degree. */
+#define FEM_MAX_VARIANTS 4
 
-/* Number of variants compiled for (p, precision) (>= 1), FEM_EDEGREE or FEM_EINVAL. */
+/* Number of variants compiled for (p, precision), p = 0..7 (>= 1), FEM_EDEGREE or FEM_EINVAL. */
 int fem_variant_count(int p, int precision);
 
 /* The variant fem_integrate launches for (p, precision), or FEM_EDEGREE / FEM_EINVAL. */
@@ -160,9 +165,14 @@ int fem_get_variant(int p, int precision);
  * variant computes the same result to the precision's tolerance. */
 int fem_set_variant(int p, int precision, int variant);
 
+/* The variant (tile configuration) that the single-launch mixed-degree kernel uses for degree
+ * p = 1..7 and precision; fixed at build time. FEM_EDEGREE / FEM_EINVAL on bad arguments. */
+int fem_mixed_variant(int p, int precision);
+
 /* Time every variant of (p, precision) on a seeded synthetic batch of nel elements (element
- * coefficients, mildly distorted cubes; 1 warm-up and 5 timed launches each, on a stream of
- * its own), choose the fastest, and, if json_path is not NULL, record the choice and the times
+ * coefficients, mildly distorted cubes; for p = 0 degrees 1..7 drawn with weights 8 - p, and
+ * the timed call includes the device bucketing; 1 warm-up and 5 timed calls each, on a stream
+ * of its own), choose the fastest, and, if json_path is not NULL, record the choice and the times
  * in that HOST file (other entries of an existing file are kept). chosen (HOST, may be NULL)
  * receives the variant, times_ms (HOST [FEM_MAX_VARIANTS], may be NULL) the mean milliseconds
  * per launch of each variant. Allocates and frees device memory for the batch and

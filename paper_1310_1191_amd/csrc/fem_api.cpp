@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "fem_kernel.h"
+#include "fem_launch.h"
 #include "fem_layout.h"
 #include "fem_tables.h"
 #include "fem_mixed.h"
@@ -28,6 +29,11 @@ hipError_t launch_f32(int p, int v, const KArgs &a, hipStream_t s, int64_t cus);
 hipError_t launch_bf16(int p, int v, const KArgs &a, hipStream_t s, int64_t cus);
 hipError_t launch_split_bf16(int p, int v, const KArgs &a, hipStream_t s, int64_t cus);
 hipError_t launch_split_f16(int p, int v, const KArgs &a, hipStream_t s, int64_t cus);
+hipError_t launch_mixed_f64(const MixedKArgs &m, int64_t nel, hipStream_t s, int64_t cus);
+hipError_t launch_mixed_f32(const MixedKArgs &m, int64_t nel, hipStream_t s, int64_t cus);
+hipError_t launch_mixed_bf16(const MixedKArgs &m, int64_t nel, hipStream_t s, int64_t cus);
+hipError_t launch_mixed_split_bf16(const MixedKArgs &m, int64_t nel, hipStream_t s, int64_t cus);
+hipError_t launch_mixed_split_f16(const MixedKArgs &m, int64_t nel, hipStream_t s, int64_t cus);
 int variants_f64(int p);
 int variants_f32(int p);
 int variants_bf16(int p);
@@ -208,8 +214,13 @@ int build_tables(State &st)
 }  // namespace
 
 namespace fem {
+// p = 0 addresses the mixed-degree path: variant 0 is the single persistent launch over every
+// degree, variant 1 one launch per degree.
+constexpr int MIXED_SINGLE = 0, MIXED_PER_DEGREE = 1;
+
 int variant_count(int prec, int p)
 {
+    if (p == 0) return 2;
     switch (prec) {
     case PREC_F64: return variants_f64(p);
     case PREC_F32: return variants_f32(p);
@@ -232,13 +243,36 @@ hipError_t dispatch_variant(int prec, int p, int v, const KArgs &a, hipStream_t 
     }
 }
 
-// The variant each (degree, precision) launches: 0 until fem_set_variant, fem_autotune or
-// fem_load_tuning chooses another.
-int g_choice[8][5] = {};
+// The variant each (degree, precision) launches: the measured default until fem_set_variant,
+// fem_autotune or fem_load_tuning chooses another. Row 0: the mixed-degree strategy.
+struct Choices {
+    int v[8][5];
+    Choices()
+    {
+        for (int prec = 0; prec < 5; ++prec) {
+            v[0][prec] = MIXED_PER_DEGREE;
+            for (int p = 1; p <= 7; ++p) v[p][prec] = default_variant(p, family_of(prec));
+        }
+    }
+    int *operator[](int p) { return v[p]; }
+};
+Choices g_choice;
 
 hipError_t dispatch(int prec, int p, const KArgs &a, hipStream_t s, int64_t cus)
 {
     return dispatch_variant(prec, p, g_choice[p][prec], a, s, cus);
+}
+
+hipError_t dispatch_mixed(int prec, const MixedKArgs &m, int64_t nel, hipStream_t s, int64_t cus)
+{
+    switch (prec) {
+    case PREC_F64: return launch_mixed_f64(m, nel, s, cus);
+    case PREC_F32: return launch_mixed_f32(m, nel, s, cus);
+    case PREC_BF16: return launch_mixed_bf16(m, nel, s, cus);
+    case PREC_SPLIT_BF16: return launch_mixed_split_bf16(m, nel, s, cus);
+    case PREC_SPLIT_F16: return launch_mixed_split_f16(m, nel, s, cus);
+    default: return hipErrorInvalidValue;
+    }
 }
 }  // namespace fem
 
@@ -389,14 +423,19 @@ int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coef
     if (mixed_bucket(nel, coeffs->degree, coeffs->workspace, s, &plan) != hipSuccess) return FEM_EHIP;
     a.a_off = coeffs->a_off;
     a.b_off = coeffs->b_off;
-    for (int pp = 7; pp >= 1; --pp) {  // heaviest degree first
-        KArgs ap = a;
+    MixedKArgs m;
+    for (int pp = 1; pp <= 7; ++pp) {
+        KArgs &ap = m.deg[pp - 1];
+        ap = a;
         set_degree(ap, pp, coeffs->precision);
         ap.nel = nel;                  // upper bound; the bucket's count is read on the device
         ap.elist = plan.elist;
         ap.seg = plan.seg + 2 * pp;
-        if (dispatch(coeffs->precision, pp, ap, s, g_cus) != hipSuccess) return FEM_EHIP;
     }
+    if (g_choice[0][coeffs->precision] == MIXED_SINGLE)
+        return dispatch_mixed(coeffs->precision, m, nel, s, g_cus) == hipSuccess ? FEM_OK : FEM_EHIP;
+    for (int pp = 7; pp >= 1; --pp)  // heaviest degree first
+        if (dispatch(coeffs->precision, pp, m.deg[pp - 1], s, g_cus) != hipSuccess) return FEM_EHIP;
     return FEM_OK;
 }
 
@@ -505,38 +544,65 @@ extern "C" {
 
 int fem_variant_count(int p, int precision)
 {
-    if (p < 1 || p > 7) return FEM_EDEGREE;
+    if (p < 0 || p > 7) return FEM_EDEGREE;
     if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16) return FEM_EINVAL;
     return variant_count(precision, p);
 }
 
 int fem_get_variant(int p, int precision)
 {
-    if (p < 1 || p > 7) return FEM_EDEGREE;
+    if (p < 0 || p > 7) return FEM_EDEGREE;
     if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16) return FEM_EINVAL;
     return g_choice[p][precision];
 }
 
 int fem_set_variant(int p, int precision, int variant)
 {
-    if (p < 1 || p > 7) return FEM_EDEGREE;
+    if (p < 0 || p > 7) return FEM_EDEGREE;
     if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16) return FEM_EINVAL;
     if (variant < 0 || variant >= variant_count(precision, p)) return FEM_ECONFIG;
     g_choice[p][precision] = variant;
     return FEM_OK;
 }
 
+int fem_mixed_variant(int p, int precision)
+{
+    if (p < 1 || p > 7) return FEM_EDEGREE;
+    if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16) return FEM_EINVAL;
+    return mixed_variant(p, family_of(precision));
+}
+
 int fem_autotune(int p, int precision, int64_t nel, const char *json_path, int *chosen,
                  double *times_ms)
 {
     if (!g_state.blob) return FEM_ENOTINIT;
-    if (p < 1 || p > 7) return FEM_EDEGREE;
+    if (p < 0 || p > 7) return FEM_EDEGREE;
     if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16 || nel <= 0) return FEM_EINVAL;
     const int nv = variant_count(precision, p);
-    const int ns = ns_of(p);
     const size_t osz = precision == FEM_FP64 ? 8 : 4;
     const TuneBatch tb = tune_batch(nel);
+    // p = 0: degrees 1..7 with weights 8 - p, interleaved; offsets by an exclusive scan
+    std::vector<int8_t> deg;
+    std::vector<int64_t> a_off(1, 0), b_off(1, 0);
+    if (p == 0) {
+        deg.resize(nel);
+        uint64_t x = 0x2545f4914f6cdd1dull;
+        for (int64_t e = 0; e < nel; ++e) {
+            x ^= x >> 12; x ^= x << 25; x ^= x >> 27;
+            int r = int(((x * 0x9e3779b97f4a7c15ull) >> 33) % 28), d = 1;
+            while (r >= 8 - d) { r -= 8 - d; ++d; }
+            deg[e] = int8_t(d);
+            const int64_t ns = ns_of(d);
+            a_off.push_back(a_off.back() + ns * ns);
+            b_off.push_back(b_off.back() + ns);
+        }
+    } else {
+        a_off.push_back(nel * int64_t(ns_of(p)) * ns_of(p));
+        b_off.push_back(nel * int64_t(ns_of(p)));
+    }
     void *d_geom = nullptr, *d_elem = nullptr, *d_A = nullptr, *d_b = nullptr;
+    void *d_deg = nullptr, *d_aoff = nullptr, *d_boff = nullptr, *d_ws = nullptr;
+    const size_t ws_bytes = p == 0 ? mixed_workspace_bytes(nel) : 0;
     hipStream_t s = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     int rc = FEM_OK;
@@ -546,8 +612,12 @@ int fem_autotune(int p, int precision, int64_t nel, const char *json_path, int *
     auto fail = [&](int code) { if (rc == FEM_OK) rc = code; };
     if (hipMalloc(&d_geom, tb.geom.size() * 8) != hipSuccess ||
         hipMalloc(&d_elem, tb.elem.size() * 8) != hipSuccess ||
-        hipMalloc(&d_A, size_t(nel) * ns * ns * osz) != hipSuccess ||
-        hipMalloc(&d_b, size_t(nel) * ns * osz) != hipSuccess)
+        hipMalloc(&d_A, size_t(a_off.back()) * osz) != hipSuccess ||
+        hipMalloc(&d_b, size_t(b_off.back()) * osz) != hipSuccess)
+        fail(FEM_ENOMEM);
+    if (rc == FEM_OK && p == 0 &&
+        (hipMalloc(&d_deg, nel) != hipSuccess || hipMalloc(&d_aoff, a_off.size() * 8) != hipSuccess ||
+         hipMalloc(&d_boff, b_off.size() * 8) != hipSuccess || hipMalloc(&d_ws, ws_bytes) != hipSuccess))
         fail(FEM_ENOMEM);
     if (rc == FEM_OK && (hipStreamCreate(&s) != hipSuccess || hipEventCreate(&ev[0]) != hipSuccess ||
                          hipEventCreate(&ev[1]) != hipSuccess))
@@ -556,21 +626,37 @@ int fem_autotune(int p, int precision, int64_t nel, const char *json_path, int *
         (hipMemcpy(d_geom, tb.geom.data(), tb.geom.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
          hipMemcpy(d_elem, tb.elem.data(), tb.elem.size() * 8, hipMemcpyHostToDevice) != hipSuccess))
         fail(FEM_EHIP);
+    if (rc == FEM_OK && p == 0 &&
+        (hipMemcpy(d_deg, deg.data(), nel, hipMemcpyHostToDevice) != hipSuccess ||
+         hipMemcpy(d_aoff, a_off.data(), a_off.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+         hipMemcpy(d_boff, b_off.data(), b_off.size() * 8, hipMemcpyHostToDevice) != hipSuccess))
+        fail(FEM_EHIP);
     fem_coeffs c;
     std::memset(&c, 0, sizeof(c));
     c.precision = precision;
     c.mode = FEM_COEF_ELEMENT;
     c.elem = static_cast<const double *>(d_elem);
+    c.degree = static_cast<const int8_t *>(d_deg);
+    c.a_off = static_cast<const int64_t *>(d_aoff);
+    c.b_off = static_cast<const int64_t *>(d_boff);
+    c.workspace = d_ws;
+    c.workspace_bytes = ws_bytes;
     KArgs a = base_args(&c, static_cast<const double *>(d_geom), d_A, d_b);
     a.nel = nel;
-    set_degree(a, p, precision);
+    if (p > 0) set_degree(a, p, precision);
+    const int saved = g_choice[p][precision];
+    auto run = [&](int v) -> bool {
+        if (p > 0) return dispatch_variant(precision, p, v, a, s, g_cus) == hipSuccess;
+        g_choice[0][precision] = v;
+        return fem_integrate(nel, 0, static_cast<const double *>(d_geom), &c, d_A, d_b, s) == FEM_OK;
+    };
     constexpr int REPS = 5;
     for (int v = 0; v < nv && rc == FEM_OK; ++v) {
-        if (dispatch_variant(precision, p, v, a, s, g_cus) != hipSuccess) { fail(FEM_EHIP); break; }
-        hipEventRecord(ev[0], s);
+        if (!run(v)) { fail(FEM_EHIP); break; }
+        (void)hipEventRecord(ev[0], s);
         for (int r = 0; r < REPS; ++r)
-            if (dispatch_variant(precision, p, v, a, s, g_cus) != hipSuccess) fail(FEM_EHIP);
-        hipEventRecord(ev[1], s);
+            if (!run(v)) fail(FEM_EHIP);
+        (void)hipEventRecord(ev[1], s);
         float ms = 0.0f;
         if (hipEventSynchronize(ev[1]) != hipSuccess || hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess)
             fail(FEM_EHIP);
@@ -578,10 +664,11 @@ int fem_autotune(int p, int precision, int64_t nel, const char *json_path, int *
         if (times_ms) times_ms[v] = entry.ms[v];
         if (v == 0 || entry.ms[v] < best_ms) { best_ms = entry.ms[v]; best = v; }
     }
+    g_choice[p][precision] = saved;
     if (ev[0]) (void)hipEventDestroy(ev[0]);
     if (ev[1]) (void)hipEventDestroy(ev[1]);
     if (s) (void)hipStreamDestroy(s);
-    (void)hipFree(d_geom); (void)hipFree(d_elem); (void)hipFree(d_A); (void)hipFree(d_b);
+    for (void *ptr : {d_geom, d_elem, d_A, d_b, d_deg, d_aoff, d_boff, d_ws}) (void)hipFree(ptr);
     if (rc != FEM_OK) return rc;
     g_choice[p][precision] = best;
     entry.variant = best;

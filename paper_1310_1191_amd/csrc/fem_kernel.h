@@ -11,17 +11,22 @@
 //     (rows: test value / derivatives, columns: trial); psi^Q = G phi^Q of section 2 is never
 //     formed. Dh_q and w_q detJ_q f go to LDS.
 //   contraction: A = B^T C with C[(q, r)][j] = sum_s Dh_q[r][s] B[(q, s)][j], a GEMM of depth
-//     4 N_Q on the matrix cores. B^T (test functions) is a constant fragment table; C (trial
-//     functions) is produced cooperatively, chunk by chunk, into a double-buffered LDS area from
-//     the 1-D Lagrange values (tensor-product structure of B), while the waves multiply the
-//     previous chunk.
-//   load vector: b_i = sum_q w_q detJ_q f phi_i(xi_q), FP64.
-//   epilogue: accumulators are scaled back (split paths) and stored unpadded, row-major.
+//     4 N_Q on the matrix cores. B^T (test functions) is a constant fragment table, staged
+//     through LDS chunk by chunk or kept resident in LDS (RES). C (trial functions) is produced
+//     from the 1-D Lagrange values (tensor-product structure of B) either cooperatively into a
+//     double-buffered LDS area while the waves multiply the previous chunk (PROD 0), or by each
+//     wave for its own column blocks, in registers, right before its MFMAs (PROD 1).
+//   load vector: b_i = sum_q w_q detJ_q f phi_i(xi_q), FP64, sum-factorised over the tensor
+//     product.
+//   epilogue: accumulators are scaled back (split paths) and stored unpadded, row-major; when a
+//     workgroup owns whole elements the tile is staged in LDS and written with aligned 16-byte
+//     stores.
 //
 // A workgroup owns work items = (group of EG elements, row tile, column tile) in a persistent
 // grid-stride loop; the next item's element data is fetched while the current one is multiplied.
 // The columns of a work item are the EG elements' trial functions side by side, NSP apart, so
-// small elements (p = 1, NSP = 8) share one MFMA column block.
+// small elements (p = 1, NSP = 8) share one MFMA column block. k_integrate runs one degree per
+// launch; k_integrate_mixed runs the buckets of every degree in one persistent launch.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -109,8 +114,10 @@ struct Shape {
     static constexpr int DSTR = 16;  // LDS stride of one point matrix (13 used)
     // column operand chunk: [k-group][column block][part][lane] x FRAGB bytes
     static constexpr int NCOL = TCB * TM;
-    static_assert(NT % NCOL == 0, "the producers cover the tile's columns");
-    static constexpr int PSTRIDE = NT / NCOL;             // points produced per pass
+    static_assert(C::PROD == 1 || NT % NCOL == 0, "the producers cover the tile's columns");
+    // PROD 1: every column block of a wave belongs to one element (the point matrices of a
+    // point are read once for all of the wave's column blocks)
+    static constexpr bool WAVE_ONE_EL = (C::EG == 1) || (NSP % (C::WN * TM)) == 0;
     static constexpr int PCH = KC * KGP;                  // points per chunk
     static constexpr int NPART = SPLIT ? 2 : 1;
     static constexpr int FRAGB = (PREC == PREC_F64) ? 32 : 16;
@@ -141,10 +148,11 @@ struct Shape {
     static constexpr size_t d_bytes = size_t(EG) * NQP * DSTR * sizeof(DT);
     static constexpr size_t off_cb = off_D + d_bytes;                     // 2 column chunks
     // Output staging: used when one workgroup owns whole elements (one row and one column
-    // tile); the tile is [NS rows][EG*NSP + 1 columns] of the output type.
+    // tile) and the tile, [NS rows][EG*NSP + 1 columns] of the output type, fits in 64 KiB;
+    // otherwise the accumulators are stored directly.
     using OT = DT;
-    static constexpr bool STAGE_OUT = (RT == 1 && CT == 1);
     static constexpr int OPITCH = EG * NSP + 1;
+    static constexpr bool STAGE_OUT = (RT == 1 && CT == 1) && size_t(NS) * OPITCH * sizeof(OT) <= 65536;
     static constexpr size_t out_bytes = STAGE_OUT ? size_t(NS) * OPITCH * sizeof(OT) : 0;
     static constexpr int NBUF = NCH > 1 ? 2 : 1;
     // row operand staged per chunk (tables not resident): [k-group][row block][16-B piece][lane]
@@ -773,7 +781,7 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
     // PPL points of lane group h in k-group kgl, written as whole 16-byte pieces.
     constexpr int HPG = S::KGP / S::PPL;
     constexpr int UNITS = S::KC * HPG * S::NCOL;
-    static_assert(NT % S::NCOL == 0, "producer columns are fixed per thread");
+    static_assert(C::PROD == 1 || NT % S::NCOL == 0, "producer columns are fixed per thread");
     const unsigned char *ldb = reinterpret_cast<const unsigned char *>(ld2);
     // padding columns read the first-direction factor from the zero copy of the table
     const int p_ab = (p_a + (p_ok ? 0 : N * N)) * (int)sizeof(DT2);
@@ -927,39 +935,71 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
         w_cb[j] = (jc / (N * N)) * (int)sizeof(DT2);
     }
     const int w_q0 = (lane / TM) * S::PPL;
-    auto produce_wave = [&](int g, int j) -> typename F::col {
-        DT vals[S::SLOTS];
+    // PROD 1: point data of k-group g for one element (the PPL points of this lane's half-wave)
+    struct Pts {
+        DT d[S::PPL][13];
+        int oa[S::PPL], ob[S::PPL], oc[S::PPL];
+    };
+    auto load_pts = [&](int g, int el, Pts &pt) {
 #pragma unroll
         for (int sub = 0; sub < S::PPL; ++sub) {
             const int q = g * S::KGP + w_q0 + sub;
-            const DT *Dh = s_D + ((size_t)w_el[j] * NQP + q) * S::DSTR;
-            DT dloc[13];
+            const DT *Dh = s_D + ((size_t)el * NQP + q) * S::DSTR;
 #pragma unroll
-            for (int uu = 0; uu < 13; ++uu) dloc[uu] = Dh[uu];
-            const DT2 fa = *reinterpret_cast<const DT2 *>(ldb + s_pt[q] + w_ab[j]);
-            const DT2 fb = *reinterpret_cast<const DT2 *>(ldb + s_pt[NQP + q] + w_bb[j]);
-            const DT2 fc = *reinterpret_cast<const DT2 *>(ldb + s_pt[2 * NQP + q] + w_cb[j]);
+            for (int uu = 0; uu < 13; ++uu) pt.d[sub][uu] = Dh[uu];
+            pt.oa[sub] = s_pt[q];
+            pt.ob[sub] = s_pt[NQP + q];
+            pt.oc[sub] = s_pt[2 * NQP + q];
+        }
+    };
+    // column block j of the wave from the point data
+    auto col_from = [&](const Pts &pt, int j) -> typename F::col {
+        DT vals[S::SLOTS];
+#pragma unroll
+        for (int sub = 0; sub < S::PPL; ++sub) {
+            const DT2 fa = *reinterpret_cast<const DT2 *>(ldb + pt.oa[sub] + w_ab[j]);
+            const DT2 fb = *reinterpret_cast<const DT2 *>(ldb + pt.ob[sub] + w_bb[j]);
+            const DT2 fc = *reinterpret_cast<const DT2 *>(ldb + pt.oc[sub] + w_cb[j]);
             DT out[4];
-            column_values<DT>(dloc, fa[0], fa[1], fb[0], fb[1], fc[0], fc[1], out);
+            column_values<DT>(pt.d[sub], fa[0], fa[1], fb[0], fb[1], fc[0], fc[1], out);
 #pragma unroll
             for (int r = 0; r < 4; ++r) vals[sub * 4 + r] = out[r];
         }
         return pack_col<PREC, DT>(vals);
     };
-    auto multiply_regs = [&](const typename F::row (&r)[C::WM], const typename F::col (&cf)[C::WN]) {
+    // the wave's column operand of the current k-group; column block j of k-group g + 1 is
+    // produced right after the MFMAs that read block j of k-group g are issued, so the
+    // production overlaps the matrix cores
+    typename F::col cfw[C::WN];
+    auto produce_first = [&]() {
+        Pts pt;
+        if constexpr (S::WAVE_ONE_EL) load_pts(0, w_el[0], pt);
 #pragma unroll
-        for (int i = 0; i < C::WM; ++i)
+        for (int j = 0; j < C::WN; ++j) {
+            if constexpr (!S::WAVE_ONE_EL) load_pts(0, w_el[j], pt);
+            cfw[j] = col_from(pt, j);
+        }
+    };
+    auto step_regs = [&](const typename F::row (&r)[C::WM], int g) {
+        const bool more = g + 1 < S::NGP;
+        Pts pt;
+        if constexpr (S::WAVE_ONE_EL) {
+            if (more) load_pts(g + 1, w_el[0], pt);
+        }
 #pragma unroll
-            for (int j = 0; j < C::WN; ++j) mma_stage<PREC, 0>(acc[i][j], r[i], cf[j]);
-        if constexpr (S::SPLIT) {
+        for (int j = 0; j < C::WN; ++j) {
 #pragma unroll
-            for (int i = 0; i < C::WM; ++i)
+            for (int i = 0; i < C::WM; ++i) mma_stage<PREC, 0>(acc[i][j], r[i], cfw[j]);
+            if constexpr (S::SPLIT) {
 #pragma unroll
-                for (int j = 0; j < C::WN; ++j) mma_stage<PREC, 1>(acc[i][j], r[i], cf[j]);
+                for (int i = 0; i < C::WM; ++i) mma_stage<PREC, 1>(acc[i][j], r[i], cfw[j]);
 #pragma unroll
-            for (int i = 0; i < C::WM; ++i)
-#pragma unroll
-                for (int j = 0; j < C::WN; ++j) mma_stage<PREC, 2>(acc[i][j], r[i], cf[j]);
+                for (int i = 0; i < C::WM; ++i) mma_stage<PREC, 2>(acc[i][j], r[i], cfw[j]);
+            }
+            if (more) {
+                if constexpr (!S::WAVE_ONE_EL) load_pts(g + 1, w_el[j], pt);
+                cfw[j] = col_from(pt, j);
+            }
         }
     };
 
@@ -973,26 +1013,13 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
                 multiply(rr, cbuf, kgl);
             }
         } else {
-            // C of the next k-group is produced while the current one is multiplied
-            typename F::col cf[C::WN];
-#pragma unroll
-            for (int j = 0; j < C::WN; ++j) cf[j] = produce_wave(ch * S::KC, j);
 #pragma unroll
             for (int kgl = 0; kgl < S::KC; ++kgl) {
                 const int g = ch * S::KC + kgl;
                 typename F::row rr[C::WM];
 #pragma unroll
                 for (int i = 0; i < C::WM; ++i) rr[i] = get_row(rbuf, kgl, i, g);
-                typename F::col cn[C::WN];
-                if (kgl + 1 < S::KC) {
-#pragma unroll
-                    for (int j = 0; j < C::WN; ++j) cn[j] = produce_wave(g + 1, j);
-                }
-                multiply_regs(rr, cf);
-                if (kgl + 1 < S::KC) {
-#pragma unroll
-                    for (int j = 0; j < C::WN; ++j) cf[j] = cn[j];
-                }
+                step_regs(rr, g);
             }
         }
     };
@@ -1001,6 +1028,7 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
     fetch_rows(0);
     store_rows(s_rb0);
     if constexpr (C::PROD == 0) produce_chunk(0, s_cb0);
+    else produce_first();
     __syncthreads();
 #pragma unroll 1
     for (int ch = 0; ch + 1 < S::NCH; ++ch) {
@@ -1143,16 +1171,16 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
     __syncthreads();  // LDS is rewritten by the next item
 }
 
-// Persistent kernel: a grid-stride loop over work items. The element count comes from the host
-// (nel) or, for the buckets of a mixed-degree call, from device memory (seg), so no host
-// synchronisation is needed between bucketing and integration.
+// The work items wi, wi + stride, wi + 2 stride, ... of one degree, processed by one workgroup
+// (a persistent loop); per-workgroup constants are loaded once. The element count comes from
+// the host (nel) or, for the buckets of a mixed-degree call, from device memory (seg), so no
+// host synchronisation is needed between bucketing and integration. Returns at once if wi is
+// past the last item. Every thread of the workgroup must call it with the same arguments.
 template <int P, int PREC, class C>
-__global__ void __launch_bounds__(C::NW * 64) __attribute__((amdgpu_waves_per_eu(C::OCC, 8)))
-k_integrate(const KArgs a)
+__device__ inline void run_items(const KArgs &a, int64_t wi, const int64_t stride, unsigned char *smem)
 {
     using S = Shape<P, PREC, C>;
     constexpr int N = S::N, NT = S::NT;
-    extern __shared__ __align__(16) unsigned char smem[];
     int64_t nel = a.nel;
     const int32_t *elist = a.elist;
     if (a.seg) {
@@ -1160,7 +1188,7 @@ k_integrate(const KArgs a)
         nel = a.seg[1];
     }
     const int64_t total = ((nel + S::EG - 1) / S::EG) * S::RT * S::CT;
-    if ((int64_t)blockIdx.x >= total) return;
+    if (wi >= total) return;
     const int tid = threadIdx.x;
     const int reclen = a.mode == 0 ? 14 : 10;
 
@@ -1210,13 +1238,12 @@ k_integrate(const KArgs a)
         }
     }
 
-    int64_t wi = blockIdx.x;
     Item it = decode_item<S>(wi, nel);
     double pf[S::PFN], pf_next[S::PFN];
     fetch_elements<S>(a, elist, it, reclen, pf);
     __syncthreads();
     for (;;) {
-        const int64_t wn = wi + gridDim.x;
+        const int64_t wn = wi + stride;
         const bool has_next = wn < total;
         const Item itn = has_next ? decode_item<S>(wn, nel) : it;
         integrate_item<P, PREC, C>(a, it, elist, reclen, smem, pf, pf_next, has_next, itn);
@@ -1226,6 +1253,56 @@ k_integrate(const KArgs a)
 #pragma unroll
         for (int k = 0; k < S::PFN; ++k) pf[k] = pf_next[k];
     }
+}
+
+// One degree per launch: a persistent grid over that degree's work items.
+template <int P, int PREC, class C>
+__global__ void __launch_bounds__(C::NW * 64) __attribute__((amdgpu_waves_per_eu(C::OCC, 8)))
+k_integrate(const KArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    run_items<P, PREC, C>(a, blockIdx.x, gridDim.x, smem);
+}
+
+// Every degree in one launch. The work items of the degrees, heaviest degree first, form one
+// index space that the persistent grid strides through; a workgroup handles its items of one
+// degree as a run (constants loaded once per run), then moves on to the next degree.
+struct MixedKArgs {
+    KArgs deg[7];  // deg[p - 1]: the bucket of degree p (seg = its {start, count})
+};
+
+template <int P, int PREC, class C>
+__device__ inline void mixed_segment(const KArgs &a, int64_t &base, unsigned char *smem)
+{
+    using S = Shape<P, PREC, C>;
+    static_assert(C::NW * 64 == 256, "the mixed-degree kernel runs 256-thread workgroups");
+    const int64_t count = a.seg[1];
+    const int64_t total = ((count + S::EG - 1) / S::EG) * S::RT * S::CT;
+    if (total > 0) {
+        const int64_t g = gridDim.x;
+        // first index >= base of the form blockIdx.x + k g, relative to base
+        const int64_t wi = (((int64_t)blockIdx.x - base) % g + g) % g;
+        if (wi < total) {
+            run_items<P, PREC, C>(a, wi, g, smem);
+            __syncthreads();  // the next degree's constants reuse the LDS
+        }
+    }
+    base += total;
+}
+
+template <int PREC, class C1, class C2, class C3, class C4, class C5, class C6, class C7>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 8)))
+k_integrate_mixed(const MixedKArgs m)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    int64_t base = 0;
+    mixed_segment<7, PREC, C7>(m.deg[6], base, smem);
+    mixed_segment<6, PREC, C6>(m.deg[5], base, smem);
+    mixed_segment<5, PREC, C5>(m.deg[4], base, smem);
+    mixed_segment<4, PREC, C4>(m.deg[3], base, smem);
+    mixed_segment<3, PREC, C3>(m.deg[2], base, smem);
+    mixed_segment<2, PREC, C2>(m.deg[1], base, smem);
+    mixed_segment<1, PREC, C1>(m.deg[0], base, smem);
 }
 
 }  // namespace fem

@@ -6,12 +6,13 @@
 
 namespace fem {
 
-constexpr int MAX_VARIANTS = 3;
+constexpr int MAX_VARIANTS = 4;
 
 // Cfg<EG, WGM, WGN, WM, WN, OCC, KC, RES, PROD> (see fem_kernel.h). For the 32-wide families
 // (FP32, BF16, split): p = 1 packs 16 elements of 8 trial functions into 4 column blocks;
-// p = 2, 3 put 4 (8) and 2 (4) elements side by side; p = 4 gives one (two) elements to a
-// workgroup; p >= 5 tile one element into row x column tiles. FP64 uses 16-wide blocks.
+// p = 2, 3 put 4 (8) and 2 (4) elements side by side; p = 4 gives one element to a workgroup
+// (variant 3: one element to each wave, 4 x 4 blocks in registers); p >= 5 tile one element
+// into row x column tiles (variant 2: 4 x 4 blocks per wave). FP64 uses 16-wide blocks.
 template <int P, int FAM, int V> struct VariantCfg { using type = void; };
 
 // -- 32-wide families --
@@ -23,15 +24,20 @@ template <> struct VariantCfg<2, MF_K16, 2> { using type = Cfg<4, 1, 4, 1, 1, 2,
 template <> struct VariantCfg<3, MF_K16, 0> { using type = Cfg<2, 1, 4, 2, 1, 2, 2, 0, 1>; };
 template <> struct VariantCfg<3, MF_K16, 1> { using type = Cfg<4, 1, 4, 2, 2, 2, 2, 1, 1>; };
 template <> struct VariantCfg<3, MF_K16, 2> { using type = Cfg<2, 1, 4, 2, 1, 2, 2, 0, 0>; };
+template <> struct VariantCfg<3, MF_K16, 3> { using type = Cfg<4, 1, 4, 2, 2, 2, 2, 0, 1>; };
 template <> struct VariantCfg<4, MF_K16, 0> { using type = Cfg<1, 1, 4, 4, 1, 2, 2, 0, 1>; };
 template <> struct VariantCfg<4, MF_K16, 1> { using type = Cfg<1, 1, 4, 4, 1, 2, 4, 0, 1>; };
 template <> struct VariantCfg<4, MF_K16, 2> { using type = Cfg<1, 1, 4, 4, 1, 2, 2, 0, 0>; };
+template <> struct VariantCfg<4, MF_K16, 3> { using type = Cfg<4, 1, 4, 4, 4, 1, 1, 0, 1>; };
 template <> struct VariantCfg<5, MF_K16, 0> { using type = Cfg<1, 1, 4, 4, 1, 1, 2, 0, 0>; };
 template <> struct VariantCfg<5, MF_K16, 1> { using type = Cfg<1, 1, 4, 4, 1, 1, 2, 0, 1>; };
+template <> struct VariantCfg<5, MF_K16, 2> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1>; };
 template <> struct VariantCfg<6, MF_K16, 0> { using type = Cfg<1, 1, 4, 6, 1, 1, 2, 0, 0>; };
 template <> struct VariantCfg<6, MF_K16, 1> { using type = Cfg<1, 1, 4, 6, 1, 1, 2, 0, 1>; };
+template <> struct VariantCfg<6, MF_K16, 2> { using type = Cfg<1, 3, 1, 4, 4, 1, 1, 0, 1>; };
 template <> struct VariantCfg<7, MF_K16, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 2, 0, 0>; };
 template <> struct VariantCfg<7, MF_K16, 1> { using type = Cfg<1, 1, 4, 8, 1, 1, 2, 0, 1>; };
+template <> struct VariantCfg<7, MF_K16, 2> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1>; };
 template <int P, int V> struct VariantCfg<P, MF_F32, V> { using type = typename VariantCfg<P, MF_K16, V>::type; };
 // -- FP64 (16-wide blocks) --
 template <> struct VariantCfg<1, MF_F64, 0> { using type = Cfg<8, 1, 4, 1, 1, 2, 2, 1, 0>; };
@@ -95,7 +101,18 @@ hipError_t launch_variant(const KArgs &a, hipStream_t s, int cus)
 template <int P, int PREC>
 int count_variants()
 {
-    return has_variant<P, PREC, 0>() + has_variant<P, PREC, 1>() + has_variant<P, PREC, 2>();
+    return has_variant<P, PREC, 0>() + has_variant<P, PREC, 1>() + has_variant<P, PREC, 2>() +
+           has_variant<P, PREC, 3>();
+}
+
+template <int P, int PREC>
+hipError_t prepare_p()
+{
+    hipError_t e = prepare_variant<P, PREC, 0>();
+    if (e == hipSuccess) e = prepare_variant<P, PREC, 1>();
+    if (e == hipSuccess) e = prepare_variant<P, PREC, 2>();
+    if (e == hipSuccess) e = prepare_variant<P, PREC, 3>();
+    return e;
 }
 
 template <int PREC>
@@ -103,13 +120,9 @@ hipError_t prepare_all()
 {
     hipError_t e = hipSuccess;
     auto one = [&](hipError_t r) { if (e == hipSuccess) e = r; };
-    one(prepare_variant<1, PREC, 0>()); one(prepare_variant<1, PREC, 1>()); one(prepare_variant<1, PREC, 2>());
-    one(prepare_variant<2, PREC, 0>()); one(prepare_variant<2, PREC, 1>()); one(prepare_variant<2, PREC, 2>());
-    one(prepare_variant<3, PREC, 0>()); one(prepare_variant<3, PREC, 1>()); one(prepare_variant<3, PREC, 2>());
-    one(prepare_variant<4, PREC, 0>()); one(prepare_variant<4, PREC, 1>()); one(prepare_variant<4, PREC, 2>());
-    one(prepare_variant<5, PREC, 0>()); one(prepare_variant<5, PREC, 1>()); one(prepare_variant<5, PREC, 2>());
-    one(prepare_variant<6, PREC, 0>()); one(prepare_variant<6, PREC, 1>()); one(prepare_variant<6, PREC, 2>());
-    one(prepare_variant<7, PREC, 0>()); one(prepare_variant<7, PREC, 1>()); one(prepare_variant<7, PREC, 2>());
+    one(prepare_p<1, PREC>()); one(prepare_p<2, PREC>()); one(prepare_p<3, PREC>());
+    one(prepare_p<4, PREC>()); one(prepare_p<5, PREC>()); one(prepare_p<6, PREC>());
+    one(prepare_p<7, PREC>());
     return e;
 }
 
@@ -120,6 +133,7 @@ hipError_t launch_pv(int v, const KArgs &a, hipStream_t s, int cus)
     case 0: return launch_variant<P, PREC, 0>(a, s, cus);
     case 1: return launch_variant<P, PREC, 1>(a, s, cus);
     case 2: return launch_variant<P, PREC, 2>(a, s, cus);
+    case 3: return launch_variant<P, PREC, 3>(a, s, cus);
     default: return hipErrorInvalidValue;
     }
 }
@@ -153,5 +167,69 @@ int variants_p(int p)
     default: return 0;
     }
 }
+
+// Variant launched for each degree before any tuning (the fastest measured on MI355X at the
+// plain-method and high-order workload sizes), and the variant each degree uses inside the
+// single-launch mixed-degree kernel (256-thread workgroups only).
+constexpr int default_variant(int p, int fam)
+{
+    if (fam == MF_F64) return 0;
+    constexpr int k16[8] = {0, 1, 1, 3, 3, 2, 2, 2};
+    constexpr int f32[8] = {0, 1, 1, 3, 1, 2, 1, 2};
+    return fam == MF_F32 ? f32[p] : k16[p];
+}
+constexpr int mixed_variant(int p, int fam)
+{
+    if (fam == MF_F64) return 0;
+    constexpr int m[8] = {0, 0, 0, 3, 3, 2, 1, 2};
+    return m[p];
+}
+
+// The single-launch mixed-degree kernel of a precision.
+template <int PREC>
+struct MixedInst {
+    template <int P> using CP = typename VariantCfg<P, family_of(PREC), mixed_variant(P, family_of(PREC))>::type;
+    template <int P> using SP = Shape<P, PREC, CP<P>>;
+    static constexpr size_t max2(size_t x, size_t y) { return x > y ? x : y; }
+    static constexpr size_t lds_bytes =
+        max2(max2(max2(SP<1>::lds_bytes, SP<2>::lds_bytes), max2(SP<3>::lds_bytes, SP<4>::lds_bytes)),
+             max2(max2(SP<5>::lds_bytes, SP<6>::lds_bytes), SP<7>::lds_bytes));
+    static inline int resident_per_cu = 1;
+    static const void *fn()
+    {
+        return reinterpret_cast<const void *>(
+            &k_integrate_mixed<PREC, CP<1>, CP<2>, CP<3>, CP<4>, CP<5>, CP<6>, CP<7>>);
+    }
+    static hipError_t prepare()
+    {
+        hipError_t e = hipSuccess;
+        if (lds_bytes > 65536)
+            e = hipFuncSetAttribute(fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+        int blocks = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn(), 256, lds_bytes);
+        if (e != hipSuccess) return e;
+        resident_per_cu = blocks > 0 ? blocks : 1;
+        return hipSuccess;
+    }
+    // The bucket sizes are read on the device; the grid is the number of workgroups the device
+    // holds at once, capped by an upper bound on the work items (every element in the bucket
+    // with the most items per element).
+    static hipError_t launch(const MixedKArgs &m, int64_t nel, hipStream_t s, int cus)
+    {
+        int64_t per_el = 1;
+        per_el = per_el > SP<7>::RT * SP<7>::CT ? per_el : SP<7>::RT * SP<7>::CT;
+        per_el = per_el > SP<6>::RT * SP<6>::CT ? per_el : SP<6>::RT * SP<6>::CT;
+        per_el = per_el > SP<5>::RT * SP<5>::CT ? per_el : SP<5>::RT * SP<5>::CT;
+        per_el = per_el > SP<4>::RT * SP<4>::CT ? per_el : SP<4>::RT * SP<4>::CT;
+        const int64_t bound = nel * per_el;
+        const int64_t cap = int64_t(cus) * resident_per_cu;
+        const int64_t grid = bound < cap ? bound : cap;
+        if (grid <= 0) return hipSuccess;
+        hipLaunchKernelGGL((k_integrate_mixed<PREC, CP<1>, CP<2>, CP<3>, CP<4>, CP<5>, CP<6>, CP<7>>),
+                           dim3((unsigned)grid), dim3(256), lds_bytes, s, m);
+        return hipGetLastError();
+    }
+};
 
 }  // namespace fem

@@ -80,6 +80,7 @@ def load():
     lib.fem_autotune.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_char_p,
                                  ctypes.POINTER(ctypes.c_int), dp]
     lib.fem_load_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]
+    lib.fem_mixed_variant.argtypes = [ctypes.c_int, ctypes.c_int]
     _lib = lib
     return lib
 
@@ -88,7 +89,7 @@ def exported_symbols():
     return ["fem_init", "fem_finalize", "fem_integrate", "fem_workspace_bytes",
             "fem_mixed_offsets", "fem_field_advance", "fem_reference_tables", "fem_strerror",
             "fem_abi_version", "fem_variant_count", "fem_get_variant", "fem_set_variant",
-            "fem_autotune", "fem_load_tuning"]
+            "fem_autotune", "fem_load_tuning", "fem_mixed_variant"]
 
 
 # ---------------------------------------------------------------------------------------------
@@ -148,7 +149,7 @@ def fem_field_advance(field: int, deltas: int, nsteps: int, step: int, stream: i
     return int(load().fem_field_advance(field, deltas, int(nsteps), step, stream))
 
 
-MAX_VARIANTS = 3
+MAX_VARIANTS = 4
 
 
 def fem_variant_count(p: int, precision: int) -> int:
@@ -181,6 +182,17 @@ def fem_autotune(p: int, precision: int, nel: int, json_path: str | None = None)
     if rc != FEM_OK:
         raise FemError(rc, "fem_autotune")
     return chosen.value, list(times)[:fem_variant_count(p, precision)]
+
+
+def fem_mixed_variant(p: int, precision: int) -> int:
+    rc = int(load().fem_mixed_variant(int(p), int(precision)))
+    if rc < 0:
+        raise FemError(rc, "fem_mixed_variant")
+    return rc
+
+
+def mixed_tile_variant(p: int, precision: int) -> int:
+    return fem_mixed_variant(p, precision)
 
 
 def fem_load_tuning(json_path: str) -> int:

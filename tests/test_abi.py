@@ -97,12 +97,16 @@ def test_variant_table_host_calls(lib):
         for prec in range(5):
             n = fem.fem_variant_count(p, prec)
             assert 1 <= n <= fem.MAX_VARIANTS
-            assert fem.fem_get_variant(p, prec) == 0
+            v0 = fem.fem_get_variant(p, prec)
+            assert 0 <= v0 < n
             fem.fem_set_variant(p, prec, n - 1)
             assert fem.fem_get_variant(p, prec) == n - 1
-            fem.fem_set_variant(p, prec, 0)
+            fem.fem_set_variant(p, prec, v0)
             assert lib.fem_set_variant(p, prec, n) == fem.FEM_ECONFIG
-    assert lib.fem_variant_count(0, 0) == fem.FEM_EDEGREE
+    for prec in range(5):  # p = 0: the mixed-degree strategies, per-degree launches by default
+        assert fem.fem_variant_count(0, prec) == 2
+        assert fem.fem_get_variant(0, prec) == 1
+    assert lib.fem_variant_count(-1, 0) == fem.FEM_EDEGREE
     assert lib.fem_variant_count(3, 5) == fem.FEM_EINVAL
     assert lib.fem_set_variant(8, 0, 0) == fem.FEM_EDEGREE
     assert lib.fem_autotune(3, 0, 100, None, None, None) == fem.FEM_ENOTINIT

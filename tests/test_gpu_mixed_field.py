@@ -51,22 +51,33 @@ def test_mixed_offsets_match_definition(fem):
         np.testing.assert_array_equal(b_off.cpu().numpy(), ref_b)
 
 
+STRATEGIES = {0: "single launch", 1: "per-degree launches"}
+
+
+@pytest.mark.parametrize("strategy", [0, 1])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "split_fp16", "split_bf16"])
-def test_mixed_degree_field_parity(fem, field_case, prec):
+def test_mixed_degree_field_parity(fem, field_case, prec, strategy):
     import torch
     w, A_ref, b_ref, a_ref_off, b_ref_off = field_case
     g, c, f, d = to_dev(w.geom, w.coef, w.field, w.degree)
     status = torch.zeros(2, dtype=torch.int32, device="cuda")
-    A, b, a_off, b_off = fem.integrate_mixed(g, c, d, precision=prec, mode=fem.FIELD, field=f,
-                                             status=status)
-    torch.cuda.synchronize()
+    code = fem.PRECISIONS[prec]
+    saved = fem.fem_get_variant(0, code)
+    fem.fem_set_variant(0, code, strategy)
+    try:
+        A, b, a_off, b_off = fem.integrate_mixed(g, c, d, precision=prec, mode=fem.FIELD, field=f,
+                                                 status=status)
+        torch.cuda.synchronize()
+    finally:
+        fem.fem_set_variant(0, code, saved)
     np.testing.assert_array_equal(a_off.cpu().numpy(), a_ref_off)
     Ag, bg = split_packed(A.double().cpu().numpy(), b.double().cpu().numpy(), a_ref_off,
                           b_ref_off, w.degree)
     Ar, br = split_packed(A_ref, b_ref, a_ref_off, b_ref_off, w.degree)
     ea = np.array([rel_fro(x[None], y[None])[0] for x, y in zip(Ag, Ar)])
     eb = np.array([rel_vec(x[None], y[None])[0] for x, y in zip(bg, br)])
-    log(f"[parity] mixed FIELD prec={prec} nel={w.nel} errA max={ea.max():.3e} errb max={eb.max():.3e}")
+    log(f"[parity] mixed FIELD prec={prec} {STRATEGIES[strategy]} nel={w.nel} "
+        f"errA max={ea.max():.3e} errb max={eb.max():.3e}")
     assert status.cpu().tolist() == [0, 0]
     assert ea.max() <= TOL_A[prec]
     assert eb.max() <= TOL_B[prec]
@@ -107,3 +118,29 @@ def test_mixed_equals_uniform_launches_bitwise(fem, field_case):
         ns = (p + 1) ** 3
         for t, e in enumerate(idx):
             assert torch.equal(A[a_off[e]:a_off[e + 1]].view(ns, ns), Au[t]), (p, e)
+
+
+@pytest.mark.parametrize("prec", ["split_fp16", "fp64"])
+def test_single_launch_equals_per_degree_launches_bitwise(fem, prec):
+    """With the per-degree launches set to the tiles the single persistent launch uses, both
+    strategies give identical bits; a larger batch makes every workgroup handle several degrees
+    in turn."""
+    import torch
+    w = synth.make(4, grid=(16, 12, 10))        # 1920 elements, degrees 1..7
+    g, c, f, d = to_dev(w.geom, w.coef, w.field, w.degree)
+    code = fem.PRECISIONS[prec]
+    saved = {p: fem.fem_get_variant(p, code) for p in range(8)}
+    # per-degree launches with the tiles the single launch uses for each degree
+    for p in range(1, 8):
+        fem.fem_set_variant(p, code, fem.mixed_tile_variant(p, code))
+    out = []
+    for strategy in (0, 1):
+        fem.fem_set_variant(0, code, strategy)
+        A, b, a_off, b_off = fem.integrate_mixed(g, c, d, precision=prec, mode=fem.FIELD, field=f)
+        torch.cuda.synchronize()
+        out.append((A, b))
+    for p, v in saved.items():
+        fem.fem_set_variant(p, code, v)
+    log(f"[mixed] {prec}: single vs per-degree, {w.nel} elements")
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1], out[1][1])

@@ -18,10 +18,10 @@ def fem():
     assert torch.cuda.is_available(), "no GPU visible"
     from paper_1310_1191_amd import fem as F
     F.fem_init(0)
+    saved = {(p, c): F.fem_get_variant(p, c) for p in range(8) for c in range(5)}
     yield F
-    for p in range(1, 8):
-        for prec in PRECS:
-            F.fem_set_variant(p, F.PRECISIONS[prec], 0)
+    for (p, c), v in saved.items():
+        F.fem_set_variant(p, c, v)
 
 
 @pytest.mark.parametrize("p", range(1, 8))
@@ -34,6 +34,7 @@ def test_every_variant_parity(fem, p, prec):
     geom, coef, A_ref, b_ref, _ = oracle_uniform(p)
     g, c = to_dev(geom, coef)
     first = None
+    v_default = fem.fem_get_variant(p, code)
     for v in range(n):
         fem.fem_set_variant(p, code, v)
         assert fem.fem_get_variant(p, code) == v
@@ -49,7 +50,7 @@ def test_every_variant_parity(fem, p, prec):
             first = bn
         else:  # the load vector does not depend on the tile configuration
             np.testing.assert_array_equal(bn, first)
-    fem.fem_set_variant(p, code, 0)
+    fem.fem_set_variant(p, code, v_default)
 
 
 def test_set_variant_rejects_missing_variant(fem):
@@ -62,7 +63,8 @@ def test_set_variant_rejects_missing_variant(fem):
 def test_autotune_writes_and_reloads_choice(fem, tmp_path):
     path = tmp_path / "tuning.json"
     seen = {}
-    for p, prec in [(2, fem.SPLIT_FP16), (4, fem.SPLIT_FP16), (3, fem.FP64)]:
+    saved = {(p, c): fem.fem_get_variant(p, c) for p in range(8) for c in range(5)}
+    for p, prec in [(2, fem.SPLIT_FP16), (4, fem.SPLIT_FP16), (3, fem.FP64), (0, fem.SPLIT_FP16)]:
         v, times = fem.fem_autotune(p, prec, 3000, str(path))
         log(f"[autotune] p={p} prec={prec} chosen={v} ms={times}")
         assert 0 <= v < fem.fem_variant_count(p, prec)
@@ -74,8 +76,9 @@ def test_autotune_writes_and_reloads_choice(fem, tmp_path):
     got = {(e["p"], e["precision"]): e["variant"] for e in doc["entries"]}
     assert got == seen
     for (p, prec) in seen:
-        fem.fem_set_variant(p, prec, 0)
+        fem.fem_set_variant(p, prec, (seen[(p, prec)] + 1) % fem.fem_variant_count(p, prec))
     assert fem.fem_load_tuning(str(path)) == len(seen)
     for (p, prec), v in seen.items():
         assert fem.fem_get_variant(p, prec) == v
-        fem.fem_set_variant(p, prec, 0)
+    for (p, c), v in saved.items():
+        fem.fem_set_variant(p, c, v)
