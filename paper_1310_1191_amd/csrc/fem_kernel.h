@@ -12,7 +12,8 @@
 //     formed. Dh_q and w_q detJ_q f go to LDS.
 //   contraction: A = B^T C with C[(q, r)][j] = sum_s Dh_q[r][s] B[(q, s)][j], a GEMM of depth
 //     4 N_Q on the matrix cores. B^T (test functions) is a constant fragment table, staged
-//     through LDS chunk by chunk or kept resident in LDS (RES). C (trial functions) is produced
+//     through LDS chunk by chunk, kept resident in LDS, or streamed by each wave straight from
+//     the L2-resident table into registers one k-group ahead (RES). C (trial functions) is produced
 //     from the 1-D Lagrange values (tensor-product structure of B) either cooperatively into a
 //     double-buffered LDS area while the waves multiply the previous chunk (PROD 0), or by each
 //     wave for its own column blocks, in registers, right before its MFMAs (PROD 1).
@@ -82,7 +83,9 @@ struct Cfg {
     static constexpr int WN = WN_;    // column blocks per wave
     static constexpr int OCC = OCC_;  // waves per SIMD the register budget must allow
     static constexpr int KC = KC_;    // k-groups per LDS chunk of the column operand
-    static constexpr int RES = RES_;  // 1: the whole row-operand table is kept in LDS
+    static constexpr int RES = RES_;  // row operand: 0 staged through LDS per chunk, 1 the whole
+                                      // table resident in LDS, 2 streamed from the table
+                                      // (L2) into registers one k-group ahead
     static constexpr int NW = WGM_ * WGN_;
 };
 
@@ -124,7 +127,8 @@ struct Shape {
     static constexpr size_t CBUF = C::PROD ? 0 : size_t(KC) * TCB * NPART * 64 * FRAGB;
     // row operand fragment bytes per lane (both parts)
     static constexpr int ROWB = (PREC == PREC_F64) ? 32 : (SPLIT ? 32 : 16);
-    static constexpr size_t ROWTAB = C::RES ? size_t(NGP) * NRB * 64 * ROWB : 0;
+    static constexpr size_t ROWTAB = C::RES == 1 ? size_t(NGP) * NRB * 64 * ROWB : 0;
+    static_assert(C::RES != 2 || C::PROD == 1, "rows streamed to registers need per-wave production");
     // element data prefetched per thread: 24 coordinates and up to 14 coefficients per element
     static constexpr int EREC = 38;
     static constexpr int PFN = (EG * EREC + NT - 1) / NT;
@@ -315,13 +319,17 @@ __device__ inline typename Frag<PREC>::col pack_col(const T v[])
         }
         return r;
     } else {
+        // hi = fp16(x) (round to nearest even); lo = fp16(x - hi), the difference formed exactly in
+        // FP32 by a mixed-precision FMA that reads hi in FP16 and writes one half of the lo pair
         SplitH r;
 #pragma unroll
         for (int t = 0; t < 8; t += 2) {
             const f32x2 x = {v[t], v[t + 1]};
             const f16x2 h = __builtin_convertvector(x, f16x2);
-            const f32x2 hf = __builtin_convertvector(h, f32x2);
-            const f16x2 l = __builtin_convertvector(x - hf, f16x2);
+            f16x2 l;
+            asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(l) : "v"(h), "v"(v[t]));
+            asm("v_fma_mixhi_f16 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+                : "+v"(l) : "v"(h), "v"(v[t + 1]));
             r.hi[t] = h[0];
             r.hi[t + 1] = h[1];
             r.lo[t] = l[0];
@@ -879,7 +887,7 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
         }
     };
     auto get_row = [&](const unsigned char *rbuf, int kgl, int i, int g) -> typename F::row {
-        if constexpr (C::RES) {
+        if constexpr (C::RES == 1) {
             return lds_row<PREC>(s_row, (size_t)g * S::NRB + rbl[i], lane);
         } else {
             const int frag = kgl * S::TRB + wm * C::WM + i;
@@ -980,11 +988,13 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
             cfw[j] = col_from(pt, j);
         }
     };
-    auto step_regs = [&](const typename F::row (&r)[C::WM], int g) {
-        const bool more = g + 1 < S::NGP;
+    // gn: the k-group produced for the next step (g + 1), or -1 for none; after_mma() runs as
+    // soon as the last MFMA that reads r is issued (the streamed-row loop reloads r there)
+    auto step_regs = [&](const typename F::row (&r)[C::WM], int g, int gn, auto &&after_mma) {
+        const bool more = gn >= 0;
         Pts pt;
         if constexpr (S::WAVE_ONE_EL) {
-            if (more) load_pts(g + 1, w_el[0], pt);
+            if (more) load_pts(gn, w_el[0], pt);
         }
 #pragma unroll
         for (int j = 0; j < C::WN; ++j) {
@@ -996,8 +1006,9 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
 #pragma unroll
                 for (int i = 0; i < C::WM; ++i) mma_stage<PREC, 2>(acc[i][j], r[i], cfw[j]);
             }
+            if (j == C::WN - 1) after_mma();
             if (more) {
-                if constexpr (!S::WAVE_ONE_EL) load_pts(g + 1, w_el[j], pt);
+                if constexpr (!S::WAVE_ONE_EL) load_pts(gn, w_el[j], pt);
                 cfw[j] = col_from(pt, j);
             }
         }
@@ -1019,29 +1030,50 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
                 typename F::row rr[C::WM];
 #pragma unroll
                 for (int i = 0; i < C::WM; ++i) rr[i] = get_row(rbuf, kgl, i, g);
-                step_regs(rr, g);
+                step_regs(rr, g, g + 1 < S::NGP ? g + 1 : -1, [] {});
             }
         }
     };
 
-    // ---- main loop: produce chunk c+1 and fetch its rows while multiplying chunk c ----
-    fetch_rows(0);
-    store_rows(s_rb0);
-    if constexpr (C::PROD == 0) produce_chunk(0, s_cb0);
-    else produce_first();
-    __syncthreads();
+    if constexpr (C::RES == 2) {
+        // ---- main loop, rows streamed: each wave loads its row fragments of k-group g + 1 from
+        // the table (L2-resident) while it multiplies k-group g; no workgroup barrier. The last
+        // iteration reloads and reproduces k-group NGP - 1, so the loop body has no branch.
+        typename F::row rr[C::WM];
+#pragma unroll
+        for (int i = 0; i < C::WM; ++i) rr[i] = load_row_off<PREC>(a, (unsigned)rbl[i], lane);
+        produce_first();
 #pragma unroll 1
-    for (int ch = 0; ch + 1 < S::NCH; ++ch) {
-        const bool odd = ch & 1;
-        fetch_rows(ch + 1);
-        // reads of the current chunk are issued before the writes of the next one, so the
-        // MFMAs do not wait behind the producer's LDS stores and the two interleave
-        consume_chunk(ch, odd ? s_cb1 : s_cb0, odd ? s_rb1 : s_rb0);
-        if constexpr (C::PROD == 0) produce_chunk(ch + 1, odd ? s_cb0 : s_cb1);
-        store_rows(odd ? s_rb0 : s_rb1);
-        if constexpr (C::PROD == 0 || !C::RES) __syncthreads();  // chunk buffers change hands
+        for (int g = 0; g < S::NGP; ++g) {
+            const int gn = g + 1 < S::NGP ? g + 1 : g;
+            // the next rows are loaded into the same registers once the last MFMA reading them
+            // is issued; their latency hides behind the production of the last column block
+            step_regs(rr, g, gn, [&] {
+#pragma unroll
+                for (int i = 0; i < C::WM; ++i)
+                    rr[i] = load_row_off<PREC>(a, (unsigned)(gn * S::NRB + rbl[i]), lane);
+            });
+        }
+    } else {
+        // ---- main loop: produce chunk c+1 and fetch its rows while multiplying chunk c ----
+        fetch_rows(0);
+        store_rows(s_rb0);
+        if constexpr (C::PROD == 0) produce_chunk(0, s_cb0);
+        else produce_first();
+        __syncthreads();
+#pragma unroll 1
+        for (int ch = 0; ch + 1 < S::NCH; ++ch) {
+            const bool odd = ch & 1;
+            fetch_rows(ch + 1);
+            // reads of the current chunk are issued before the writes of the next one, so the
+            // MFMAs do not wait behind the producer's LDS stores and the two interleave
+            consume_chunk(ch, odd ? s_cb1 : s_cb0, odd ? s_rb1 : s_rb0);
+            if constexpr (C::PROD == 0) produce_chunk(ch + 1, odd ? s_cb0 : s_cb1);
+            store_rows(odd ? s_rb0 : s_rb1);
+            if constexpr (C::PROD == 0 || !C::RES) __syncthreads();  // chunk buffers change hands
+        }
+        consume_chunk(S::NCH - 1, ((S::NCH - 1) & 1) ? s_cb1 : s_cb0, ((S::NCH - 1) & 1) ? s_rb1 : s_rb0);
     }
-    consume_chunk(S::NCH - 1, ((S::NCH - 1) & 1) ? s_cb1 : s_cb0, ((S::NCH - 1) & 1) ? s_rb1 : s_rb0);
 
     using OT = typename S::OT;
     __syncthreads();  // every wave is done with the point matrices and the chunks
@@ -1220,7 +1252,7 @@ __device__ inline void run_items(const KArgs &a, int64_t wi, const int64_t strid
             s_pt[2 * S::NQP + q] = ok ? (q / (N * N)) * ROWBYTES : 0;
         }
     }
-    if constexpr (C::RES) {
+    if constexpr (C::RES == 1) {
         // [frag][part][lane] x 16 B (split), [frag][lane] x 16 B or 32 B otherwise
         typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
         u32x4 *dst = reinterpret_cast<u32x4 *>(smem + S::off_row);
