@@ -153,7 +153,7 @@ int fem_reference_tables(int p, double *gauss_x, double *gauss_w, double *lobatt
  * 0 integrates every degree in one persistent launch (the work items of all degrees form one
  * index space, heaviest degree first, each degree with a fixed tile configuration); 1 (the
  * default) issues one launch per degree, each with the variant chosen for that degree. */
-#define FEM_MAX_VARIANTS 4
+#define FEM_MAX_VARIANTS 6
 
 /* Number of variants compiled for (p, precision), p = 0..7 (>= 1), FEM_EDEGREE or FEM_EINVAL. */
 int fem_variant_count(int p, int precision);

@@ -51,6 +51,7 @@ struct DegreeDev {
     const double *xq = nullptr, *wq = nullptr, *LD64 = nullptr;
     const float *LD32 = nullptr;
     const void *row[5][2] = {};
+    const void *bcol[3] = {};  // column-operand factor table B per family (FP32, FP32, FP64)
     float c_bound = 0.0f;
 };
 
@@ -117,7 +118,7 @@ int build_tables(State &st)
 {
     HostBlob hb;
     struct Offs {
-        size_t xq, wq, ld64, ld32, row[5][2];
+        size_t xq, wq, ld64, ld32, row[5][2], bcol[3];
         bool has_lo[5];
         float c_bound;
     } offs[8];
@@ -140,6 +141,32 @@ int build_tables(State &st)
         o.ld32 = hb.put(ld32.data(), ld32.size() * 4);
         o.c_bound = float(F16_C_TARGET / t.bmax);
         const std::vector<double> B = reference_operand(t);
+        // B in the column-operand fragment layout of each family: [group][table block][lane][slot]
+        // holds B[(q, s)][j] for the lane's column j; one table block per 32 (16) columns of an
+        // element, or a single block whose lanes cycle through the Ns columns when several
+        // elements share a block (p = 1)
+        for (int fam = 0; fam < 3; ++fam) {
+            const int tm = fam_tm(fam), ns = ns_of(p), nrb = rblocks_of(p, fam);
+            const bool packed = 2 * ns <= tm;
+            const int tb = packed ? 1 : nrb, ng = groups_padded(p, fam), sl = fam_slots(fam);
+            const size_t count = size_t(ng) * tb * 64 * sl;
+            std::vector<double> v(count, 0.0);
+            for (int g = 0; g < ng; ++g)
+                for (int b = 0; b < tb; ++b)
+                    for (int l = 0; l < 64; ++l)
+                        for (int sv = 0; sv < sl; ++sv) {
+                            const int q = slot_point(fam, g, l, sv), r = slot_comp(sv);
+                            const int j = packed ? (l % tm) % ns : b * tm + l % tm;
+                            if (q < ns && j < ns)
+                                v[((size_t(g) * tb + b) * 64 + l) * sl + sv] = B[(size_t(q) * 4 + r) * ns + j];
+                        }
+            if (fam == MF_F64) {
+                o.bcol[fam] = hb.put(v.data(), count * 8);
+            } else {
+                std::vector<float> f(v.begin(), v.end());
+                o.bcol[fam] = hb.put(f.data(), count * 4);
+            }
+        }
         for (int prec = 0; prec < 5; ++prec) {
             const int fam = family_of(prec);
             const int ng = groups_padded(p, fam), nrb = rblocks_of(p, fam), sl = fam_slots(fam);
@@ -203,6 +230,7 @@ int build_tables(State &st)
         dd.LD64 = reinterpret_cast<const double *>(base + o.ld64);
         dd.LD32 = reinterpret_cast<const float *>(base + o.ld32);
         dd.c_bound = o.c_bound;
+        for (int fam = 0; fam < 3; ++fam) dd.bcol[fam] = base + o.bcol[fam];
         for (int prec = 0; prec < 5; ++prec) {
             dd.row[prec][0] = base + o.row[prec][0];
             dd.row[prec][1] = o.has_lo[prec] ? base + o.row[prec][1] : nullptr;
@@ -301,6 +329,7 @@ void set_degree(KArgs &a, int p, int prec)
     a.LD32 = d.LD32;
     a.row_hi = d.row[prec][0];
     a.row_lo = d.row[prec][1];
+    a.bcol = d.bcol[family_of(prec)];
     a.c_bound = d.c_bound;
     a.row_scale_inv = prec == PREC_SPLIT_F16 ? 1.0f / F16_TABLE_SCALE : 1.0f;
 }

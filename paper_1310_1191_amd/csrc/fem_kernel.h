@@ -68,11 +68,13 @@ struct KArgs {
     const float *LD32;       // the same, rounded to FP32
     const void *row_hi;      // row-operand fragment table (fem_layout.h)
     const void *row_lo;      // second table of the split paths, else null
+    const void *bcol;        // B[(q, s)][j] in the column-operand fragment layout (FP32; FP64 path FP64)
     float c_bound;           // split paths: 2^15 / max_{q,j} sum_r |B[(q,r)][j]|
     float row_scale_inv;     // 1 / (power-of-two scale of the row table)
 };
 
-template <int EG_, int WGM_, int WGN_, int WM_, int WN_, int OCC_, int KC_, int RES_, int PROD_ = 0>
+template <int EG_, int WGM_, int WGN_, int WM_, int WN_, int OCC_, int KC_, int RES_, int PROD_ = 0,
+          int BT_ = 0>
 struct Cfg {
     static constexpr int PROD = PROD_;  // 0: C chunks produced by the whole workgroup into LDS;
                                         // 1: each wave produces its own C fragments in registers
@@ -86,6 +88,9 @@ struct Cfg {
     static constexpr int RES = RES_;  // row operand: 0 staged through LDS per chunk, 1 the whole
                                       // table resident in LDS, 2 streamed from the table
                                       // (L2) into registers one k-group ahead
+    static constexpr int BT = BT_;    // PROD 1 only: 1 reads the B factors of the column operand
+                                      // from a precomputed table instead of forming them from the
+                                      // 1-D Lagrange tables
     static constexpr int NW = WGM_ * WGN_;
 };
 
@@ -944,9 +949,22 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
     }
     const int w_q0 = (lane / TM) * S::PPL;
     // PROD 1: point data of k-group g for one element (the PPL points of this lane's half-wave)
+    // BT: byte offset of the lane's slots in the B table per column block, and the group stride
+    constexpr bool PACKED = 2 * NS <= TM;  // several elements share a column block (p = 1)
+    constexpr int TBN = PACKED ? 1 : S::NRB;
+    constexpr size_t BGSTRIDE = size_t(TBN) * 64 * S::SLOTS * sizeof(DT);
+    int w_bt[C::WN];
+#pragma unroll
+    for (int j = 0; j < C::WN; ++j) {
+        const int cbg = ct * S::TCB + cbt0 + j;
+        const int cbc = cbg < S::NCB ? cbg : S::NCB - 1;
+        const int jj = (cbc * TM + lane % TM) % S::NSP;
+        w_bt[j] = ((PACKED ? 0 : jj / TM) * 64 + lane) * S::SLOTS * (int)sizeof(DT);
+    }
     struct Pts {
         DT d[S::PPL][13];
         int oa[S::PPL], ob[S::PPL], oc[S::PPL];
+        DT b[C::WN][S::SLOTS];
     };
     auto load_pts = [&](int g, int el, Pts &pt) {
 #pragma unroll
@@ -955,9 +973,24 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
             const DT *Dh = s_D + ((size_t)el * NQP + q) * S::DSTR;
 #pragma unroll
             for (int uu = 0; uu < 13; ++uu) pt.d[sub][uu] = Dh[uu];
-            pt.oa[sub] = s_pt[q];
-            pt.ob[sub] = s_pt[NQP + q];
-            pt.oc[sub] = s_pt[2 * NQP + q];
+            if constexpr (!C::BT) {
+                pt.oa[sub] = s_pt[q];
+                pt.ob[sub] = s_pt[NQP + q];
+                pt.oc[sub] = s_pt[2 * NQP + q];
+            }
+        }
+    };
+    // BT: the lane's B factors of column block j at k-group g (L2-resident table)
+    auto load_btab = [&](int g, int j, Pts &pt) {
+        if constexpr (C::BT) {
+            const char *src = reinterpret_cast<const char *>(a.bcol) + (size_t)g * BGSTRIDE + w_bt[j];
+            typedef DT dt4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+            for (int h = 0; h < S::SLOTS / 4; ++h) {
+                const dt4 x = *reinterpret_cast<const dt4 *>(src + h * 4 * sizeof(DT));
+#pragma unroll
+                for (int u = 0; u < 4; ++u) pt.b[j][h * 4 + u] = x[u];
+            }
         }
     };
     // column block j of the wave from the point data
@@ -965,11 +998,20 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
         DT vals[S::SLOTS];
 #pragma unroll
         for (int sub = 0; sub < S::PPL; ++sub) {
-            const DT2 fa = *reinterpret_cast<const DT2 *>(ldb + pt.oa[sub] + w_ab[j]);
-            const DT2 fb = *reinterpret_cast<const DT2 *>(ldb + pt.ob[sub] + w_bb[j]);
-            const DT2 fc = *reinterpret_cast<const DT2 *>(ldb + pt.oc[sub] + w_cb[j]);
             DT out[4];
-            column_values<DT>(pt.d[sub], fa[0], fa[1], fb[0], fb[1], fc[0], fc[1], out);
+            if constexpr (C::BT) {
+                const DT *bq = pt.b[j] + sub * 4;
+                const DT *d = pt.d[sub];
+                out[0] = d[0] * bq[0] + d[1] * bq[1] + d[2] * bq[2] + d[3] * bq[3];
+                out[1] = d[4] * bq[1] + d[5] * bq[2] + d[6] * bq[3];
+                out[2] = d[7] * bq[1] + d[8] * bq[2] + d[9] * bq[3];
+                out[3] = d[10] * bq[1] + d[11] * bq[2] + d[12] * bq[3];
+            } else {
+                const DT2 fa = *reinterpret_cast<const DT2 *>(ldb + pt.oa[sub] + w_ab[j]);
+                const DT2 fb = *reinterpret_cast<const DT2 *>(ldb + pt.ob[sub] + w_bb[j]);
+                const DT2 fc = *reinterpret_cast<const DT2 *>(ldb + pt.oc[sub] + w_cb[j]);
+                column_values<DT>(pt.d[sub], fa[0], fa[1], fb[0], fb[1], fc[0], fc[1], out);
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r) vals[sub * 4 + r] = out[r];
         }
@@ -985,6 +1027,7 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
 #pragma unroll
         for (int j = 0; j < C::WN; ++j) {
             if constexpr (!S::WAVE_ONE_EL) load_pts(0, w_el[j], pt);
+            load_btab(0, j, pt);
             cfw[j] = col_from(pt, j);
         }
     };
@@ -994,7 +1037,11 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
         const bool more = gn >= 0;
         Pts pt;
         if constexpr (S::WAVE_ONE_EL) {
-            if (more) load_pts(gn, w_el[0], pt);
+            if (more) {
+                load_pts(gn, w_el[0], pt);
+#pragma unroll
+                for (int j = 0; j < C::WN; ++j) load_btab(gn, j, pt);
+            }
         }
 #pragma unroll
         for (int j = 0; j < C::WN; ++j) {
@@ -1008,10 +1055,21 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
             }
             if (j == C::WN - 1) after_mma();
             if (more) {
-                if constexpr (!S::WAVE_ONE_EL) load_pts(gn, w_el[j], pt);
+                if constexpr (!S::WAVE_ONE_EL) {
+                    load_pts(gn, w_el[j], pt);
+                    load_btab(gn, j, pt);
+                }
                 cfw[j] = col_from(pt, j);
             }
         }
+#ifdef FEM_SCHED_VALU_PER_MFMA
+        // interleave: one MFMA, then a few VALU instructions, repeated
+#pragma unroll
+        for (int k = 0; k < C::WM * C::WN * (S::SPLIT ? 3 : 1); ++k) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, FEM_SCHED_VALU_PER_MFMA, 0);
+        }
+#endif
     };
 
     auto consume_chunk = [&](int ch, const unsigned char *cbuf, const unsigned char *rbuf) {

@@ -6,7 +6,7 @@
 
 namespace fem {
 
-constexpr int MAX_VARIANTS = 4;
+constexpr int MAX_VARIANTS = 6;
 
 // Cfg<EG, WGM, WGN, WM, WN, OCC, KC, RES, PROD> (see fem_kernel.h). For the 32-wide families
 // (FP32, BF16, split): p = 1 packs 16 elements of 8 trial functions into 4 column blocks;
@@ -21,23 +21,30 @@ template <> struct VariantCfg<1, MF_K16, 1> { using type = Cfg<16, 1, 4, 1, 1, 3
 template <> struct VariantCfg<2, MF_K16, 0> { using type = Cfg<4, 1, 4, 1, 1, 3, 2, 1, 1>; };
 template <> struct VariantCfg<2, MF_K16, 1> { using type = Cfg<8, 1, 4, 1, 2, 2, 2, 1, 1>; };
 template <> struct VariantCfg<2, MF_K16, 2> { using type = Cfg<4, 1, 4, 1, 1, 3, 1, 2, 1>; };
+template <> struct VariantCfg<2, MF_K16, 3> { using type = Cfg<4, 1, 4, 1, 1, 3, 1, 2, 1, 1>; };
 template <> struct VariantCfg<3, MF_K16, 0> { using type = Cfg<2, 1, 4, 2, 1, 2, 2, 0, 1>; };
 template <> struct VariantCfg<3, MF_K16, 1> { using type = Cfg<4, 1, 4, 2, 2, 2, 2, 1, 1>; };
 template <> struct VariantCfg<3, MF_K16, 2> { using type = Cfg<4, 1, 4, 2, 2, 2, 1, 2, 1>; };
 template <> struct VariantCfg<3, MF_K16, 3> { using type = Cfg<4, 1, 4, 2, 2, 2, 2, 0, 1>; };
+template <> struct VariantCfg<3, MF_K16, 4> { using type = Cfg<4, 1, 4, 2, 2, 2, 1, 2, 1, 1>; };
 template <> struct VariantCfg<4, MF_K16, 0> { using type = Cfg<1, 1, 4, 4, 1, 2, 2, 0, 1>; };
 template <> struct VariantCfg<4, MF_K16, 1> { using type = Cfg<2, 1, 4, 4, 2, 1, 1, 0, 1>; };
-template <> struct VariantCfg<4, MF_K16, 2> { using type = Cfg<1, 1, 4, 4, 1, 2, 2, 0, 0>; };
+template <> struct VariantCfg<4, MF_K16, 2> { using type = Cfg<2, 1, 4, 4, 2, 2, 1, 0, 1>; };
 template <> struct VariantCfg<4, MF_K16, 3> { using type = Cfg<4, 1, 4, 4, 4, 1, 1, 0, 1>; };
+template <> struct VariantCfg<4, MF_K16, 4> { using type = Cfg<4, 1, 4, 4, 4, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<4, MF_K16, 5> { using type = Cfg<2, 1, 4, 4, 2, 2, 1, 0, 1, 1>; };
 template <> struct VariantCfg<5, MF_K16, 0> { using type = Cfg<1, 1, 4, 4, 1, 1, 2, 0, 0>; };
 template <> struct VariantCfg<5, MF_K16, 1> { using type = Cfg<1, 1, 4, 4, 1, 1, 2, 0, 1>; };
 template <> struct VariantCfg<5, MF_K16, 2> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1>; };
+template <> struct VariantCfg<5, MF_K16, 3> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1, 1>; };
 template <> struct VariantCfg<6, MF_K16, 0> { using type = Cfg<1, 1, 4, 6, 1, 1, 2, 0, 0>; };
 template <> struct VariantCfg<6, MF_K16, 1> { using type = Cfg<1, 1, 4, 6, 1, 1, 2, 0, 1>; };
 template <> struct VariantCfg<6, MF_K16, 2> { using type = Cfg<1, 3, 1, 4, 4, 1, 1, 0, 1>; };
+template <> struct VariantCfg<6, MF_K16, 3> { using type = Cfg<1, 3, 1, 4, 4, 1, 1, 0, 1, 1>; };
 template <> struct VariantCfg<7, MF_K16, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 2, 0, 0>; };
 template <> struct VariantCfg<7, MF_K16, 1> { using type = Cfg<1, 1, 4, 8, 1, 1, 2, 0, 1>; };
 template <> struct VariantCfg<7, MF_K16, 2> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1>; };
+template <> struct VariantCfg<7, MF_K16, 3> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1, 1>; };
 template <int P, int V> struct VariantCfg<P, MF_F32, V> { using type = typename VariantCfg<P, MF_K16, V>::type; };
 // -- FP64 (16-wide blocks) --
 template <> struct VariantCfg<1, MF_F64, 0> { using type = Cfg<8, 1, 4, 1, 1, 2, 2, 1, 0>; };
@@ -102,7 +109,7 @@ template <int P, int PREC>
 int count_variants()
 {
     return has_variant<P, PREC, 0>() + has_variant<P, PREC, 1>() + has_variant<P, PREC, 2>() +
-           has_variant<P, PREC, 3>();
+           has_variant<P, PREC, 3>() + has_variant<P, PREC, 4>() + has_variant<P, PREC, 5>();
 }
 
 template <int P, int PREC>
@@ -112,6 +119,8 @@ hipError_t prepare_p()
     if (e == hipSuccess) e = prepare_variant<P, PREC, 1>();
     if (e == hipSuccess) e = prepare_variant<P, PREC, 2>();
     if (e == hipSuccess) e = prepare_variant<P, PREC, 3>();
+    if (e == hipSuccess) e = prepare_variant<P, PREC, 4>();
+    if (e == hipSuccess) e = prepare_variant<P, PREC, 5>();
     return e;
 }
 
@@ -134,6 +143,8 @@ hipError_t launch_pv(int v, const KArgs &a, hipStream_t s, int cus)
     case 1: return launch_variant<P, PREC, 1>(a, s, cus);
     case 2: return launch_variant<P, PREC, 2>(a, s, cus);
     case 3: return launch_variant<P, PREC, 3>(a, s, cus);
+    case 4: return launch_variant<P, PREC, 4>(a, s, cus);
+    case 5: return launch_variant<P, PREC, 5>(a, s, cus);
     default: return hipErrorInvalidValue;
     }
 }
@@ -174,8 +185,8 @@ int variants_p(int p)
 constexpr int default_variant(int p, int fam)
 {
     if (fam == MF_F64) return 0;
-    constexpr int k16[8] = {0, 1, 2, 2, 3, 2, 2, 2};
-    constexpr int f32[8] = {0, 1, 1, 3, 3, 2, 1, 2};
+    constexpr int k16[8] = {0, 1, 3, 4, 3, 2, 2, 2};
+    constexpr int f32[8] = {0, 1, 1, 3, 5, 2, 1, 2};
     return fam == MF_F32 ? f32[p] : k16[p];
 }
 constexpr int mixed_variant(int p, int fam)

@@ -149,7 +149,7 @@ def fem_field_advance(field: int, deltas: int, nsteps: int, step: int, stream: i
     return int(load().fem_field_advance(field, deltas, int(nsteps), step, stream))
 
 
-MAX_VARIANTS = 4
+MAX_VARIANTS = 6
 
 
 def fem_variant_count(p: int, precision: int) -> int:

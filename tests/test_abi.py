@@ -111,3 +111,15 @@ def test_variant_table_host_calls(lib):
     assert lib.fem_set_variant(8, 0, 0) == fem.FEM_EDEGREE
     assert lib.fem_autotune(3, 0, 100, None, None, None) == fem.FEM_ENOTINIT
     assert lib.fem_load_tuning(b"/nonexistent.json", None) == fem.FEM_ENOTINIT
+
+
+def test_variant_numbering_is_contiguous():
+    """Variants of each (degree, family) are numbered 0..n-1 with no gap, so every index below
+    fem_variant_count names a compiled kernel."""
+    src = open(os.path.join(ROOT, "paper_1310_1191_amd", "csrc", "fem_launch.h")).read()
+    seen = {}
+    for p, fam, v in re.findall(r"VariantCfg<(\d), (MF_\w+), (\d)>", src):
+        seen.setdefault((p, fam), []).append(int(v))
+    assert seen
+    for key, vs in seen.items():
+        assert sorted(vs) == list(range(len(vs))), key
