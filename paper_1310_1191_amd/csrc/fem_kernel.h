@@ -162,7 +162,15 @@ struct Shape {
     using OT = DT;
     static constexpr int OPITCH = EG * NSP + 1;
     static constexpr bool STAGE_OUT = (RT == 1 && CT == 1) && size_t(NS) * OPITCH * sizeof(OT) <= 65536;
-    static constexpr size_t out_bytes = STAGE_OUT ? size_t(NS) * OPITCH * sizeof(OT) : 0;
+    // Otherwise, when every wave owns whole elements (all rows and exactly one element's columns),
+    // each wave stages one row block of its element at a time, [TM rows][NSP + 1 columns], and
+    // writes it as one contiguous range of 16-byte vectors (whole cache lines, no partial-line
+    // writes to HBM).
+    static constexpr bool STAGE_WAVE = !STAGE_OUT && C::PROD == 1 && RT == 1 && CT == 1 &&
+                                       C::WN * TM == NSP && C::WM * TM >= NS && C::WGM == 1;
+    static constexpr int WPITCH = NSP + 1;
+    static constexpr size_t out_bytes = STAGE_OUT ? size_t(NS) * OPITCH * sizeof(OT)
+                                      : STAGE_WAVE ? size_t(C::NW) * TM * WPITCH * sizeof(OT) : 0;
     static constexpr int NBUF = NCH > 1 ? 2 : 1;
     // row operand staged per chunk (tables not resident): [k-group][row block][16-B piece][lane]
     static constexpr int RPART = ROWB / 16;                                 // 16-B pieces per lane
@@ -1182,7 +1190,58 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
 
     // ---- epilogue: unpadded row-major store ----
     OT *outA = reinterpret_cast<OT *>(a.out_A);
-    if constexpr (S::STAGE_OUT) {
+    if constexpr (S::STAGE_WAVE) {
+        // This wave's element: column blocks cbt0 .. cbt0 + WN - 1 of the tile are its columns.
+        const int el = (cbt0 * TM) / S::NSP;
+        OT *stage = reinterpret_cast<OT *>(smem + S::off_D) + (size_t)wave * TM * S::WPITCH;
+        if (el < neg) {
+            const int64_t e = element_id(elist, e0 + el);
+            OT *dst0 = outA + (a.a_off ? a.a_off[e] : e * (int64_t)NS * NS);
+            const float us = S::SPLIT ? a.row_scale_inv / split_scale(s_dmax[el], a.c_bound)
+                                      : a.row_scale_inv;
+            constexpr int VW = 16 / sizeof(OT);
+            typedef OT vec_t __attribute__((ext_vector_type(VW)));
+#pragma unroll
+            for (int i = 0; i < C::WM; ++i) {
+                const int r0 = i * TM;
+                if (r0 >= NS) break;
+                const int nrow = NS - r0 < TM ? NS - r0 : TM;
+#pragma unroll
+                for (int j = 0; j < C::WN; ++j)
+#pragma unroll
+                    for (int v = 0; v < F::ACC_N; ++v) {
+                        const int rl = acc_row<FAM>(lane, v);
+                        const OT x = (PREC == PREC_F64) ? OT(acc[i][j][v]) : OT(acc[i][j][v] * us);
+                        stage[rl * S::WPITCH + j * TM + (lane % TM)] = x;
+                    }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // rows r0 .. r0 + nrow - 1 are one contiguous range of the element's matrix
+                OT *dst = dst0 + (int64_t)r0 * NS;
+                const int n = nrow * NS;
+                const int mis = (int)((reinterpret_cast<uintptr_t>(dst) & 15) / sizeof(OT));
+                const int head = mis ? (VW - mis < n ? VW - mis : n) : 0;
+                const int nvec = (n - head) / VW;
+                const int tail0 = head + nvec * VW;
+                if (lane < head) dst[lane] = stage[(lane / NS) * S::WPITCH + lane % NS];
+                for (int k = lane; k < nvec; k += 64) {
+                    const int idx = head + k * VW;
+                    vec_t vv;
+#pragma unroll
+                    for (int u = 0; u < VW; ++u) {
+                        const int x = idx + u;
+                        vv[u] = stage[(x / NS) * S::WPITCH + x % NS];
+                    }
+                    *reinterpret_cast<vec_t *>(dst + idx) = vv;
+                }
+                for (int x = tail0 + lane; x < n; x += 64) dst[x] = stage[(x / NS) * S::WPITCH + x % NS];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
+    } else if constexpr (S::STAGE_OUT) {
         // The workgroup owns whole elements: stage [row][column] in LDS, then write each
         // element's contiguous Ns x Ns block with aligned 16-byte stores.
         OT *s_out = reinterpret_cast<OT *>(smem + S::off_D);
