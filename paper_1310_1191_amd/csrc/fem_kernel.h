@@ -160,17 +160,19 @@ struct Shape {
     // tile) and the tile, [NS rows][EG*NSP + 1 columns] of the output type, fits in 64 KiB;
     // otherwise the accumulators are stored directly.
     using OT = DT;
-    static constexpr int OPITCH = EG * NSP + 1;
-    static constexpr bool STAGE_OUT = (RT == 1 && CT == 1) && size_t(NS) * OPITCH * sizeof(OT) <= 65536;
+    // Staged images hold the output exactly as it lies in memory (row-major, pitch NS), shifted
+    // by the destination's misalignment so that 16-byte global vectors are 16-byte LDS vectors.
+    static constexpr int VW = 16 / sizeof(OT);
+    static constexpr int IMG = (NS * NS + 2 * VW - 1) / VW * VW;      // one element
+    static constexpr bool STAGE_OUT = (RT == 1 && CT == 1) && size_t(EG) * IMG * sizeof(OT) <= 65536;
     // Otherwise, when every wave owns whole elements (all rows and exactly one element's columns),
-    // each wave stages one row block of its element at a time, [TM rows][NSP + 1 columns], and
-    // writes it as one contiguous range of 16-byte vectors (whole cache lines, no partial-line
-    // writes to HBM).
+    // each wave stages one row block of its element at a time and writes it as one contiguous
+    // range of 16-byte vectors (whole cache lines, no partial-line writes to HBM).
     static constexpr bool STAGE_WAVE = !STAGE_OUT && C::PROD == 1 && RT == 1 && CT == 1 &&
                                        C::WN * TM == NSP && C::WM * TM >= NS && C::WGM == 1;
-    static constexpr int WPITCH = NSP + 1;
-    static constexpr size_t out_bytes = STAGE_OUT ? size_t(NS) * OPITCH * sizeof(OT)
-                                      : STAGE_WAVE ? size_t(C::NW) * TM * WPITCH * sizeof(OT) : 0;
+    static constexpr int WIMG = (TM * NS + 2 * VW - 1) / VW * VW;     // one row block
+    static constexpr size_t out_bytes = STAGE_OUT ? size_t(EG) * IMG * sizeof(OT)
+                                      : STAGE_WAVE ? size_t(C::NW) * WIMG * sizeof(OT) : 0;
     static constexpr int NBUF = NCH > 1 ? 2 : 1;
     // row operand staged per chunk (tables not resident): [k-group][row block][16-B piece][lane]
     static constexpr int RPART = ROWB / 16;                                 // 16-B pieces per lane
@@ -1190,67 +1192,74 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
 
     // ---- epilogue: unpadded row-major store ----
     OT *outA = reinterpret_cast<OT *>(a.out_A);
+    static_assert(S::off_D % 16 == 0, "staged images start 16-byte aligned");
+    constexpr int VW = S::VW;
+    typedef OT vec_t __attribute__((ext_vector_type(VW)));
+    // Write n values from a staged image to dst (img[x] belongs at dst[x]; img is 16-byte aligned
+    // where dst is) with whole 16-byte vectors between a scalar head and tail. Threads t of NTH.
+    auto copy_out = [&](OT *dst, const OT *img, int n, int t, int nth) {
+        const int mis = (int)((reinterpret_cast<uintptr_t>(dst) & 15) / sizeof(OT));
+        const int head = mis ? (VW - mis < n ? VW - mis : n) : 0;
+        const int nvec = (n - head) / VW;
+        const int tail0 = head + nvec * VW;
+        if (t < head) dst[t] = img[t];
+        for (int k = t; k < nvec; k += nth) {
+            const int idx = head + k * VW;
+            *reinterpret_cast<vec_t *>(dst + idx) = *reinterpret_cast<const vec_t *>(img + idx);
+        }
+        for (int x = tail0 + t; x < n; x += nth) dst[x] = img[x];
+    };
+    // offset of an image so that image index x sits at the same position within 16 bytes as dst[x]
+    auto img_shift = [](const OT *dst) { return (int)((reinterpret_cast<uintptr_t>(dst) & 15) / sizeof(OT)); };
     if constexpr (S::STAGE_WAVE) {
         // This wave's element: column blocks cbt0 .. cbt0 + WN - 1 of the tile are its columns.
         const int el = (cbt0 * TM) / S::NSP;
-        OT *stage = reinterpret_cast<OT *>(smem + S::off_D) + (size_t)wave * TM * S::WPITCH;
+        OT *stage = reinterpret_cast<OT *>(smem + S::off_D) + (size_t)wave * S::WIMG;
         if (el < neg) {
             const int64_t e = element_id(elist, e0 + el);
             OT *dst0 = outA + (a.a_off ? a.a_off[e] : e * (int64_t)NS * NS);
             const float us = S::SPLIT ? a.row_scale_inv / split_scale(s_dmax[el], a.c_bound)
                                       : a.row_scale_inv;
-            constexpr int VW = 16 / sizeof(OT);
-            typedef OT vec_t __attribute__((ext_vector_type(VW)));
 #pragma unroll
             for (int i = 0; i < C::WM; ++i) {
                 const int r0 = i * TM;
                 if (r0 >= NS) break;
                 const int nrow = NS - r0 < TM ? NS - r0 : TM;
+                OT *dst = dst0 + (int64_t)r0 * NS;
+                OT *img = stage + img_shift(dst);
 #pragma unroll
-                for (int j = 0; j < C::WN; ++j)
+                for (int j = 0; j < C::WN; ++j) {
+                    const int jj = j * TM + (lane % TM);
 #pragma unroll
                     for (int v = 0; v < F::ACC_N; ++v) {
                         const int rl = acc_row<FAM>(lane, v);
-                        const OT x = (PREC == PREC_F64) ? OT(acc[i][j][v]) : OT(acc[i][j][v] * us);
-                        stage[rl * S::WPITCH + j * TM + (lane % TM)] = x;
+                        if (jj < NS && rl < nrow)
+                            img[rl * NS + jj] = (PREC == PREC_F64) ? OT(acc[i][j][v]) : OT(acc[i][j][v] * us);
                     }
+                }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 // rows r0 .. r0 + nrow - 1 are one contiguous range of the element's matrix
-                OT *dst = dst0 + (int64_t)r0 * NS;
-                const int n = nrow * NS;
-                const int mis = (int)((reinterpret_cast<uintptr_t>(dst) & 15) / sizeof(OT));
-                const int head = mis ? (VW - mis < n ? VW - mis : n) : 0;
-                const int nvec = (n - head) / VW;
-                const int tail0 = head + nvec * VW;
-                if (lane < head) dst[lane] = stage[(lane / NS) * S::WPITCH + lane % NS];
-                for (int k = lane; k < nvec; k += 64) {
-                    const int idx = head + k * VW;
-                    vec_t vv;
-#pragma unroll
-                    for (int u = 0; u < VW; ++u) {
-                        const int x = idx + u;
-                        vv[u] = stage[(x / NS) * S::WPITCH + x % NS];
-                    }
-                    *reinterpret_cast<vec_t *>(dst + idx) = vv;
-                }
-                for (int x = tail0 + lane; x < n; x += 64) dst[x] = stage[(x / NS) * S::WPITCH + x % NS];
+                copy_out(dst, img, nrow * NS, lane, 64);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
     } else if constexpr (S::STAGE_OUT) {
-        // The workgroup owns whole elements: stage [row][column] in LDS, then write each
-        // element's contiguous Ns x Ns block with aligned 16-byte stores.
+        // The workgroup owns whole elements: stage each element's matrix as it lies in memory,
+        // then write each element's contiguous Ns x Ns block with aligned 16-byte stores.
         OT *s_out = reinterpret_cast<OT *>(smem + S::off_D);
 #pragma unroll
         for (int j = 0; j < C::WN; ++j) {
             const int cb = ct * S::TCB + cbt0 + j;
             if (cb >= S::NCB) continue;
             const int col = cb * TM + (lane % TM);
-            const int el = col / S::NSP;
+            const int el = col / S::NSP, jj = col % S::NSP;
+            if (jj >= NS || el >= neg) continue;
+            const int64_t e = element_id(elist, e0 + el);
+            OT *img = s_out + el * S::IMG + img_shift(outA + (a.a_off ? a.a_off[e] : e * (int64_t)NS * NS));
             const float us = S::SPLIT ? a.row_scale_inv / split_scale(s_dmax[el], a.c_bound)
                                       : a.row_scale_inv;
 #pragma unroll
@@ -1260,35 +1269,17 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
                 for (int v = 0; v < F::ACC_N; ++v) {
                     const int row = (rb0 + i) * TM + acc_row<FAM>(lane, v);
                     if (row < NS) {
-                        if constexpr (PREC == PREC_F64) s_out[row * S::OPITCH + col] = acc[i][j][v];
-                        else s_out[row * S::OPITCH + col] = acc[i][j][v] * us;
+                        if constexpr (PREC == PREC_F64) img[row * NS + jj] = acc[i][j][v];
+                        else img[row * NS + jj] = acc[i][j][v] * us;
                     }
                 }
             }
         }
         __syncthreads();
-        constexpr int VW = 16 / sizeof(OT);
         for (int el = 0; el < neg; ++el) {
             const int64_t e = element_id(elist, e0 + el);
             OT *dst = outA + (a.a_off ? a.a_off[e] : e * (int64_t)NS * NS);
-            const OT *src = s_out + el * S::NSP;
-            const int mis = (int)((reinterpret_cast<uintptr_t>(dst) & 15) / sizeof(OT));
-            const int head = mis ? (VW - mis < NS * NS ? VW - mis : NS * NS) : 0;
-            const int nvec = (NS * NS - head) / VW;
-            const int tail0 = head + nvec * VW;
-            if (tid < head) dst[tid] = src[(tid / NS) * S::OPITCH + tid % NS];
-            for (int k = tid; k < nvec; k += NT) {
-                const int idx = head + k * VW;
-                typedef OT vec_t __attribute__((ext_vector_type(VW)));
-                vec_t vv;
-#pragma unroll
-                for (int u = 0; u < VW; ++u) {
-                    const int x = idx + u;
-                    vv[u] = src[(x / NS) * S::OPITCH + x % NS];
-                }
-                *reinterpret_cast<vec_t *>(dst + idx) = vv;
-            }
-            for (int x = tail0 + tid; x < NS * NS; x += NT) dst[x] = src[(x / NS) * S::OPITCH + x % NS];
+            copy_out(dst, s_out + el * S::IMG + img_shift(dst), NS * NS, tid, NT);
         }
     } else {
 #pragma unroll
