@@ -164,12 +164,16 @@ struct Shape {
     // by the destination's misalignment so that 16-byte global vectors are 16-byte LDS vectors.
     static constexpr int VW = 16 / sizeof(OT);
     static constexpr int IMG = (NS * NS + 2 * VW - 1) / VW * VW;      // one element
-    static constexpr bool STAGE_OUT = (RT == 1 && CT == 1) && size_t(EG) * IMG * sizeof(OT) <= 65536;
-    // Otherwise, when every wave owns whole elements (all rows and exactly one element's columns),
-    // each wave stages one row block of its element at a time and writes it as one contiguous
-    // range of 16-byte vectors (whole cache lines, no partial-line writes to HBM).
-    static constexpr bool STAGE_WAVE = !STAGE_OUT && C::PROD == 1 && RT == 1 && CT == 1 &&
-                                       C::WN * TM == NSP && C::WM * TM >= NS && C::WGM == 1;
+    // When every wave owns whole elements (all rows and exactly one element's columns), each
+    // wave can stage one row block of its element at a time and write it as one contiguous range
+    // of 16-byte vectors (whole cache lines, no partial-line writes to HBM). Single-wave
+    // workgroups always do so (it needs the least LDS); otherwise the whole tile is staged when
+    // it fits in 64 KiB.
+    static constexpr bool WAVE_OWNS_EL = C::PROD == 1 && RT == 1 && CT == 1 && C::WN * TM == NSP &&
+                                         C::WM * TM >= NS && C::WGM == 1;
+    static constexpr bool STAGE_OUT = (RT == 1 && CT == 1) && size_t(EG) * IMG * sizeof(OT) <= 65536 &&
+                                      !(WAVE_OWNS_EL && C::NW == 1);
+    static constexpr bool STAGE_WAVE = !STAGE_OUT && WAVE_OWNS_EL;
     static constexpr int WIMG = (TM * NS + 2 * VW - 1) / VW * VW;     // one row block
     static constexpr size_t out_bytes = STAGE_OUT ? size_t(EG) * IMG * sizeof(OT)
                                       : STAGE_WAVE ? size_t(C::NW) * WIMG * sizeof(OT) : 0;
