@@ -32,11 +32,11 @@ template <> struct VariantCfg<3, MF_K16, 2> { using type = Cfg<4, 1, 4, 2, 2, 2,
 template <> struct VariantCfg<3, MF_K16, 3> { using type = Cfg<4, 1, 4, 2, 2, 2, 2, 0, 1>; };
 template <> struct VariantCfg<3, MF_K16, 4> { using type = Cfg<4, 1, 4, 2, 2, 2, 1, 2, 1, 1>; };
 template <> struct VariantCfg<3, MF_K16, 5> { using type = Cfg<1, 1, 1, 2, 2, 2, 1, 2, 1, 1>; };
-template <> struct VariantCfg<4, MF_K16, 0> { using type = Cfg<1, 1, 4, 4, 1, 2, 2, 0, 1>; };
+template <> struct VariantCfg<4, MF_K16, 0> { using type = Cfg<1, 1, 1, 4, 4, 1, 1, 0, 1, 0>; };
 template <> struct VariantCfg<4, MF_K16, 1> { using type = Cfg<2, 1, 4, 4, 2, 1, 1, 0, 1>; };
 template <> struct VariantCfg<4, MF_K16, 2> { using type = Cfg<2, 1, 4, 4, 2, 2, 1, 0, 1>; };
 template <> struct VariantCfg<4, MF_K16, 3> { using type = Cfg<4, 1, 4, 4, 4, 1, 1, 0, 1>; };
-template <> struct VariantCfg<4, MF_K16, 4> { using type = Cfg<4, 1, 4, 4, 4, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<4, MF_K16, 4> { using type = Cfg<1, 1, 1, 4, 4, 1, 1, 0, 1, 1>; };
 template <> struct VariantCfg<4, MF_K16, 5> { using type = Cfg<2, 1, 4, 4, 2, 2, 1, 0, 1, 1>; };
 template <> struct VariantCfg<5, MF_K16, 0> { using type = Cfg<1, 1, 4, 4, 1, 1, 2, 0, 0>; };
 template <> struct VariantCfg<5, MF_K16, 1> { using type = Cfg<1, 1, 4, 4, 1, 1, 2, 0, 1>; };
@@ -197,7 +197,7 @@ constexpr int default_variant(int p, int fam)
 constexpr int mixed_variant(int p, int fam)
 {
     if (fam == MF_F64) return 0;
-    constexpr int m[8] = {0, 0, 0, 3, 3, 2, 1, 2};
+    constexpr int m[8] = {0, 1, 3, 4, 3, 2, 1, 2};
     return m[p];
 }
 

@@ -82,3 +82,27 @@ def test_autotune_writes_and_reloads_choice(fem, tmp_path):
         assert fem.fem_get_variant(p, prec) == v
     for (p, c), v in saved.items():
         fem.fem_set_variant(p, c, v)
+
+
+@pytest.mark.parametrize("p", range(1, 8))
+def test_every_variant_field_mode(fem, p):
+    """Coefficient fields (FIELD mode) through every compiled variant of the split-FP16 path."""
+    import oracle
+    import torch
+    from paper_1310_1191_amd import synth
+    w = synth.make(4, grid=(5, 3, 2) if p <= 4 else (3, 2, 1))
+    A_ref, b_ref, _ = oracle.integrate(w.geom, w.coef, p=p, mode=oracle.FIELD, field=w.field)
+    g, c, f = (torch.from_numpy(x).cuda() for x in (w.geom, w.coef, w.field))
+    code = fem.SPLIT_FP16
+    v_default = fem.fem_get_variant(p, code)
+    try:
+        for v in range(fem.fem_variant_count(p, code)):
+            fem.fem_set_variant(p, code, v)
+            A, b = fem.integrate(g, c, p, precision="split_fp16", mode=fem.FIELD, field=f)
+            torch.cuda.synchronize()
+            ea = rel_fro(A.double().cpu().numpy(), A_ref)
+            eb = rel_vec(b.double().cpu().numpy(), b_ref)
+            log(f"[variant FIELD] p={p} v={v} errA max={ea.max():.3e} errb max={eb.max():.3e}")
+            assert ea.max() <= TOL_A["split_fp16"] and eb.max() <= TOL_B["split_fp16"]
+    finally:
+        fem.fem_set_variant(p, code, v_default)
