@@ -175,8 +175,13 @@ struct Shape {
                                       !(WAVE_OWNS_EL && C::NW == 1);
     static constexpr bool STAGE_WAVE = !STAGE_OUT && WAVE_OWNS_EL;
     static constexpr int WIMG = (TM * NS + 2 * VW - 1) / VW * VW;     // one row block
+    // Otherwise a workgroup that owns whole elements with one row of waves stages one row block
+    // of all its elements at a time.
+    static constexpr bool STAGE_RB = !STAGE_OUT && !STAGE_WAVE && RT == 1 && CT == 1 && C::WGM == 1 &&
+                                     size_t(EG) * WIMG * sizeof(OT) <= 65536;
     static constexpr size_t out_bytes = STAGE_OUT ? size_t(EG) * IMG * sizeof(OT)
-                                      : STAGE_WAVE ? size_t(C::NW) * WIMG * sizeof(OT) : 0;
+                                      : STAGE_WAVE ? size_t(C::NW) * WIMG * sizeof(OT)
+                                      : STAGE_RB ? size_t(EG) * WIMG * sizeof(OT) : 0;
     static constexpr int NBUF = NCH > 1 ? 2 : 1;
     // row operand staged per chunk (tables not resident): [k-group][row block][16-B piece][lane]
     static constexpr int RPART = ROWB / 16;                                 // 16-B pieces per lane
@@ -1250,6 +1255,40 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
+        }
+    } else if constexpr (S::STAGE_RB) {
+        // One row block of every element at a time (all waves hold the same row blocks).
+        OT *s_img = reinterpret_cast<OT *>(smem + S::off_D);
+#pragma unroll
+        for (int i = 0; i < C::WM; ++i) {
+            const int r0 = i * TM;
+            if (r0 >= NS) break;
+            const int nrow = NS - r0 < TM ? NS - r0 : TM;
+#pragma unroll
+            for (int j = 0; j < C::WN; ++j) {
+                const int cb = cbt0 + j;
+                const int col = cb * TM + (lane % TM);
+                const int el = col / S::NSP, jj = col % S::NSP;
+                if (jj >= NS || el >= neg) continue;
+                const int64_t e = element_id(elist, e0 + el);
+                OT *dst = outA + (a.a_off ? a.a_off[e] : e * (int64_t)NS * NS) + (int64_t)r0 * NS;
+                OT *img = s_img + el * S::WIMG + img_shift(dst);
+                const float us = S::SPLIT ? a.row_scale_inv / split_scale(s_dmax[el], a.c_bound)
+                                          : a.row_scale_inv;
+#pragma unroll
+                for (int v = 0; v < F::ACC_N; ++v) {
+                    const int rl = acc_row<FAM>(lane, v);
+                    if (rl < nrow)
+                        img[rl * NS + jj] = (PREC == PREC_F64) ? OT(acc[i][j][v]) : OT(acc[i][j][v] * us);
+                }
+            }
+            __syncthreads();
+            for (int el = 0; el < neg; ++el) {
+                const int64_t e = element_id(elist, e0 + el);
+                OT *dst = outA + (a.a_off ? a.a_off[e] : e * (int64_t)NS * NS) + (int64_t)r0 * NS;
+                copy_out(dst, s_img + el * S::WIMG + img_shift(dst), nrow * NS, tid, NT);
+            }
+            __syncthreads();
         }
     } else if constexpr (S::STAGE_OUT) {
         // The workgroup owns whole elements: stage each element's matrix as it lies in memory,

@@ -26,8 +26,8 @@ template <> struct VariantCfg<2, MF_K16, 2> { using type = Cfg<4, 1, 1, 1, 4, 2,
 template <> struct VariantCfg<2, MF_K16, 3> { using type = Cfg<4, 1, 4, 1, 1, 3, 1, 2, 1, 1>; };
 template <> struct VariantCfg<2, MF_K16, 4> { using type = Cfg<1, 1, 1, 1, 1, 3, 1, 2, 1, 1>; };
 template <> struct VariantCfg<2, MF_K16, 5> { using type = Cfg<2, 1, 1, 1, 2, 3, 1, 2, 1, 1>; };
-template <> struct VariantCfg<3, MF_K16, 0> { using type = Cfg<2, 1, 1, 2, 4, 1, 1, 2, 1, 1>; };
-template <> struct VariantCfg<3, MF_K16, 1> { using type = Cfg<4, 1, 4, 2, 2, 2, 2, 1, 1>; };
+template <> struct VariantCfg<3, MF_K16, 0> { using type = Cfg<4, 1, 4, 2, 2, 3, 1, 2, 1, 1>; };
+template <> struct VariantCfg<3, MF_K16, 1> { using type = Cfg<1, 1, 1, 2, 2, 3, 1, 2, 1, 1>; };
 template <> struct VariantCfg<3, MF_K16, 2> { using type = Cfg<4, 1, 4, 2, 2, 2, 1, 2, 1>; };
 template <> struct VariantCfg<3, MF_K16, 3> { using type = Cfg<4, 1, 4, 2, 2, 2, 2, 0, 1>; };
 template <> struct VariantCfg<3, MF_K16, 4> { using type = Cfg<4, 1, 4, 2, 2, 2, 1, 2, 1, 1>; };
