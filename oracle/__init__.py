@@ -3,7 +3,8 @@
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may import
 this package. It wraps ``fem_oracle.c`` (plain C, OpenMP over elements), which follows
 Algorithm 2 of the paper (section 2) with the element entry of eq. (sum_int) (section 5.1),
-specialised to a scalar convection-diffusion-reaction form. It shares no code with the HIP
+specialised to a scalar convection-diffusion-reaction form, and the paper's vector model problem
+(linear elastostatics, section 5.1). It shares no code with the HIP
 library; the two meet only in the seeded input generators.
 """
 from __future__ import annotations
@@ -53,6 +54,9 @@ def _load():
     lib.oracle_integrate.argtypes = [
         ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+    lib.oracle_integrate_elastic.argtypes = [
+        ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
     lib.oracle_max_threads.restype = ctypes.c_int
     _lib = lib
@@ -153,3 +157,22 @@ def integrate(geom, coef, p: int | None = None, degree=None, mode: int = ELEMENT
     if rc != 0:
         raise ValueError("oracle_integrate: bad arguments")
     return A, b, flags, a_off, b_off
+
+
+def integrate_elastic(geom, coef, p: int, threads: int = 0, with_b: bool = True):
+    """Linear elastostatics (section 5.1) in FP64: coef [nel, 5] = (E, nu, f1, f2, f3).
+    Returns (A [nel, 3, 3, Ns, Ns], b [nel, 3, Ns] or None, flags [nel]); block A[e, i, k]
+    couples test component i with trial component k."""
+    geom = np.ascontiguousarray(geom, dtype=np.float64)
+    coef = np.ascontiguousarray(coef, dtype=np.float64)
+    nel = geom.shape[0]
+    assert geom.shape[1:] == (8, 3) and coef.shape == (nel, 5)
+    ns = (p + 1) ** 3 if 1 <= p <= 7 else 1
+    A = np.zeros((nel, 3, 3, ns, ns))
+    b = np.zeros((nel, 3, ns)) if with_b else None
+    flags = np.zeros(nel, dtype=np.int32)
+    rc = _load().oracle_integrate_elastic(nel, p, _vp(geom), _vp(coef), _vp(A), _vp(b), _vp(flags),
+                                         threads)
+    if rc != 0:
+        raise ValueError("oracle_integrate_elastic: bad arguments")
+    return A, b, flags

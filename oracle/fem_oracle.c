@@ -319,6 +319,144 @@ int oracle_integrate(int64_t nel, int p, const int8_t *degree, const double *geo
     return 0;
 }
 
+/* ---------------------------------------------------------------------------------------------
+ * Vector problem of section 5.1: linear elastostatics, d = 3 components, the same shape
+ * functions for every component. Element entry (eq. (sum_int)) for test function s of
+ * component i and trial function r of component k:
+ *
+ *   A[(i,s)][(k,r)] = sum_q c_ijkl (d phi_r / d x_l) (d phi_s / d x_j) detJ w_q
+ *
+ * with the isotropic tensor from the element's Young modulus E and Poisson ratio nu (the two
+ * material parameters of section 5.1):
+ *   lambda = E nu / ((1 + nu)(1 - 2 nu)),  mu = E / (2 (1 + nu)),
+ *   c_ijkl = lambda delta_ij delta_kl + mu (delta_ik delta_jl + delta_il delta_jk).
+ * Load vector (body force f, constant per element): b[(i,s)] = sum_q f_i phi_s detJ w_q.
+ * ------------------------------------------------------------------------------------------- */
+static int integrate_elastic_one(int p, const double *X, const double *rec, double *A, double *bvec)
+{
+    const int n = p + 1;
+    const int ns = n * n * n;
+    double gx[MAX_N], gw[MAX_N], nodes[MAX_N];
+    double L[MAX_N][MAX_N], D[MAX_N][MAX_N]; /* [point][node] */
+    double phi[MAX_NS][4], psi[MAX_NS][4];
+    int flags = 0;
+
+    oracle_gauss_legendre(n, gx, gw);
+    oracle_gll_nodes(p, nodes);
+    for (int q = 0; q < n; ++q)
+        oracle_lagrange(n, nodes, gx[q], L[q], D[q]);
+    for (int t = 0; t < 24; ++t)
+        if (!isfinite(X[t]))
+            flags |= ORACLE_FLAG_NONFINITE;
+
+    const double E = rec[0], nu = rec[1];
+    const double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    const double mu = E / (2.0 * (1.0 + nu));
+    double c[3][3][3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l)
+                    c[i][j][k][l] = lam * (i == j) * (k == l) + mu * ((i == k) * (j == l) + (i == l) * (j == k));
+
+    memset(A, 0, sizeof(double) * 9 * (size_t)ns * ns);
+    if (bvec)
+        memset(bvec, 0, sizeof(double) * 3 * (size_t)ns);
+
+    for (int q3 = 0; q3 < n; ++q3)
+        for (int q2 = 0; q2 < n; ++q2)
+            for (int q1 = 0; q1 < n; ++q1) {
+                const double xi[3] = {gx[q1], gx[q2], gx[q3]};
+                const double wq = gw[q1] * gw[q2] * gw[q3];
+                for (int cc = 0; cc < n; ++cc)
+                    for (int bb = 0; bb < n; ++bb)
+                        for (int aa = 0; aa < n; ++aa) {
+                            int r = aa + n * bb + n * n * cc;
+                            phi[r][0] = L[q1][aa] * L[q2][bb] * L[q3][cc];
+                            phi[r][1] = D[q1][aa] * L[q2][bb] * L[q3][cc];
+                            phi[r][2] = L[q1][aa] * D[q2][bb] * L[q3][cc];
+                            phi[r][3] = L[q1][aa] * L[q2][bb] * D[q3][cc];
+                        }
+                double J[3][3] = {{0}};
+                for (int v = 0; v < 8; ++v) {
+                    const double s1 = (v & 1) ? 1.0 : -1.0;
+                    const double s2 = (v & 2) ? 1.0 : -1.0;
+                    const double s3 = (v & 4) ? 1.0 : -1.0;
+                    const double f1 = 1.0 + s1 * xi[0], f2 = 1.0 + s2 * xi[1], f3 = 1.0 + s3 * xi[2];
+                    const double dN[3] = {s1 * f2 * f3 / 8.0, f1 * s2 * f3 / 8.0, f1 * f2 * s3 / 8.0};
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b)
+                            J[a][b] += X[v * 3 + a] * dN[b];
+                }
+                const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                   J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                   J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+                if (!(det > 0.0))
+                    flags |= ORACLE_FLAG_DETJ;
+                double Ji[3][3];
+                Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+                Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+                Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+                Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+                Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+                Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+                Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+                Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+                Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+                /* d phi / d x_l = sum_m (d phi / d xi_m)(d xi_m / d x_l), a column of J^{-1} */
+                for (int r = 0; r < ns; ++r) {
+                    psi[r][0] = phi[r][0];
+                    for (int l = 0; l < 3; ++l)
+                        psi[r][1 + l] = Ji[0][l] * phi[r][1] + Ji[1][l] * phi[r][2] + Ji[2][l] * phi[r][3];
+                }
+                const double dw = det * wq;
+                for (int i = 0; i < 3; ++i)
+                    for (int k = 0; k < 3; ++k) {
+                        double *blk = A + (size_t)(3 * i + k) * ns * ns;
+                        for (int s = 0; s < ns; ++s)
+                            for (int r = 0; r < ns; ++r) {
+                                double t = 0.0;
+                                for (int j = 0; j < 3; ++j)
+                                    for (int l = 0; l < 3; ++l)
+                                        t += c[i][j][k][l] * psi[r][1 + l] * psi[s][1 + j];
+                                blk[(size_t)s * ns + r] += dw * t;
+                            }
+                    }
+                if (bvec)
+                    for (int i = 0; i < 3; ++i)
+                        for (int s = 0; s < ns; ++s)
+                            bvec[(size_t)i * ns + s] += dw * rec[2 + i] * psi[s][0];
+            }
+    for (size_t t = 0; t < 9 * (size_t)ns * ns; ++t)
+        if (!isfinite(A[t]))
+            flags |= ORACLE_FLAG_NONFINITE;
+    return flags;
+}
+
+int oracle_integrate_elastic(int64_t nel, int p, const double *geom, const double *coef,
+                             double *out_A, double *out_b, int32_t *flags, int nthreads)
+{
+    if (nel < 0)
+        return -1;
+    if (nel == 0)
+        return 0;
+    if (!geom || !coef || !out_A || p < 1 || p > 7)
+        return -1;
+    const int64_t ns = (int64_t)(p + 1) * (p + 1) * (p + 1);
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t e = 0; e < nel; ++e) {
+        int fl = integrate_elastic_one(p, geom + e * 24, coef + e * 5, out_A + e * 9 * ns * ns,
+                                       out_b ? out_b + e * 3 * ns : NULL);
+        if (flags)
+            flags[e] = fl;
+    }
+    return 0;
+}
+
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP

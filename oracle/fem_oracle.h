@@ -72,6 +72,17 @@ int oracle_integrate(int64_t nel, int p, const int8_t *degree, const double *geo
                      const int64_t *b_off, double *out_A, double *out_b, int32_t *flags,
                      int nthreads);
 
+/* Linear elastostatics (section 5.1, eq. (sum_int) with the isotropic tensor c_ijkl of the
+ * element's Young modulus and Poisson ratio), uniform degree p = 1..7.
+ *   coef   [nel][5] = E, nu, f1, f2, f3 (body force, constant per element)
+ *   out_A  [nel][3][3][Ns][Ns]: block (i, k) couples test component i with trial component k,
+ *          entry [s][r] = sum_q c_ijkl (d phi_r/d x_l)(d phi_s/d x_j) detJ w_q
+ *   out_b  [nel][3][Ns]: b[i][s] = sum_q f_i phi_s detJ w_q, may be NULL
+ *   flags  as for oracle_integrate, may be NULL
+ * Returns 0, or -1 on an argument error. */
+int oracle_integrate_elastic(int64_t nel, int p, const double *geom, const double *coef,
+                             double *out_A, double *out_b, int32_t *flags, int nthreads);
+
 /* Number of OpenMP threads a call with nthreads = 0 uses. */
 int oracle_max_threads(void);
 
