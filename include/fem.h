@@ -74,15 +74,23 @@ typedef enum {
  *                     (a, k1, k2, k3, theta) = 175 doubles. Field s at x is
  *                     g_s(x) = sum_m a_sm sin(2 pi (k_sm . x) + theta_sm) and at each
  *                     quadrature point x_q: K = Q diag(10^g0, 10^g1, 10^g2) Q^T,
- *                     b = (g3, g4, g5), c = (1 + g6) / 2; f stays per element. */
-typedef enum { FEM_COEF_ELEMENT = 0, FEM_COEF_FIELD = 1 } fem_coef_mode;
+ *                     b = (g3, g4, g5), c = (1 + g6) / 2; f stays per element.
+ *   FEM_COEF_ELASTIC  the vector model problem of section 5.1, linear elastostatics with the
+ *                     isotropic tensor c_ijkl = lambda d_ij d_kl + mu (d_ik d_jl + d_il d_jk)
+ *                     of each element's Young modulus E and Poisson ratio nu:
+ *                     elem[e][5] = E, nu, f1, f2, f3 (body force). Uniform p only. The
+ *                     element matrix is the 3 x 3 block matrix of Ns x Ns blocks
+ *                     A[(i,s)][(k,r)] = sum_q c_ijkl d_l phi_r d_j phi_s w_q detJ_q (eq.
+ *                     (sum_int)), stored out_A[e][i][k][s][r]; out_b[e][i][s] =
+ *                     sum_q f_i phi_s w_q detJ_q. Both are 9 (3) times the scalar sizes. */
+typedef enum { FEM_COEF_ELEMENT = 0, FEM_COEF_FIELD = 1, FEM_COEF_ELASTIC = 2 } fem_coef_mode;
 
 /* Per-call description of the coefficients and of optional mixed-degree data. HOST struct,
  * read during the call only; the pointers inside are DEVICE pointers. */
 typedef struct fem_coeffs {
     int32_t precision;       /* fem_precision; FEM_FP64 -> out_A/out_b are double, else float */
     int32_t mode;            /* fem_coef_mode */
-    const double *elem;      /* [nel][14] or [nel][10] FP64 records, see fem_coef_mode */
+    const double *elem;      /* [nel][14], [nel][10] or [nel][5] FP64 records, see fem_coef_mode */
     const double *field;     /* [175] FP64, FIELD mode only, else ignored */
     const int8_t *degree;    /* [nel] per-element degree 1..7 when p == 0, else ignored */
     const int64_t *a_off;    /* [nel+1] element offsets (in entries) into out_A when p == 0 */

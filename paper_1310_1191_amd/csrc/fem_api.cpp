@@ -332,6 +332,8 @@ void set_degree(KArgs &a, int p, int prec)
     a.bcol = d.bcol[family_of(prec)];
     a.c_bound = d.c_bound;
     a.row_scale_inv = prec == PREC_SPLIT_F16 ? 1.0f / F16_TABLE_SCALE : 1.0f;
+    a.a_stride = int64_t(ns_of(p)) * ns_of(p);
+    a.b_stride = ns_of(p);
 }
 
 }  // namespace
@@ -432,14 +434,38 @@ int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coef
     if (!g_state.blob) return FEM_ENOTINIT;
     if (nel < 0 || !coeffs) return FEM_EINVAL;
     if (coeffs->precision < FEM_FP64 || coeffs->precision > FEM_SPLIT_FP16) return FEM_EINVAL;
-    if (coeffs->mode != FEM_COEF_ELEMENT && coeffs->mode != FEM_COEF_FIELD) return FEM_EINVAL;
+    if (coeffs->mode != FEM_COEF_ELEMENT && coeffs->mode != FEM_COEF_FIELD &&
+        coeffs->mode != FEM_COEF_ELASTIC)
+        return FEM_EINVAL;
     if (p < 0 || p > 7) return FEM_EDEGREE;
+    if (coeffs->mode == FEM_COEF_ELASTIC && p == 0) return FEM_EINVAL;
     if (p == 0 && !coeffs->degree) return FEM_EDEGREE;
     if (nel == 0) return FEM_OK;
     if (!geom || !out_A || !coeffs->elem) return FEM_EINVAL;
     if (coeffs->mode == FEM_COEF_FIELD && !coeffs->field) return FEM_EINVAL;
     const hipStream_t s = (hipStream_t)stream;
     KArgs a = base_args(coeffs, geom, out_A, out_b);
+    if (p > 0 && coeffs->mode == FEM_COEF_ELASTIC) {
+        // nine blocks (test component i, trial component k), one launch each, written with
+        // element strides 9 Ns^2 and 3 Ns; the load vector of component i comes with block (i, i)
+        a.nel = nel;
+        set_degree(a, p, coeffs->precision);
+        const int64_t nsq = a.a_stride, ns = a.b_stride;
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) {
+                KArgs ab = a;
+                ab.comp_i = i;
+                ab.comp_k = k;
+                ab.a_base = (3 * i + k) * nsq;
+                ab.a_stride = 9 * nsq;
+                ab.b_base = i * ns;
+                ab.b_stride = 3 * ns;
+                ab.out_b = (i == k) ? out_b : nullptr;
+                ab.status = (i == 0 && k == 0) ? coeffs->status : nullptr;
+                if (dispatch(coeffs->precision, p, ab, s, g_cus) != hipSuccess) return FEM_EHIP;
+            }
+        return FEM_OK;
+    }
     if (p > 0) {
         a.nel = nel;
         set_degree(a, p, coeffs->precision);

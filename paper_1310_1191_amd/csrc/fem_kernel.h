@@ -62,7 +62,10 @@ struct KArgs {
     void *out_A;
     void *out_b;             // may be null
     int32_t *status;         // [2] or null
-    int32_t mode;            // 0 ELEMENT, 1 FIELD
+    int32_t mode;            // 0 ELEMENT, 1 FIELD, 2 ELASTIC (block comp_i, comp_k)
+    int32_t comp_i, comp_k;  // ELASTIC: test and trial component of this launch's block
+    int64_t a_base, a_stride;  // without a_off: element e's matrix starts at a_base + e a_stride
+    int64_t b_base, b_stride;  // without b_off: element e's vector starts at b_base + e b_stride
     const double *xq, *wq;   // [n] Gauss points and weights
     const double *LD64;      // [n][n][2]: (L, D)[gauss point][node]
     const float *LD32;       // the same, rounded to FP32
@@ -710,6 +713,20 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
             bv[2] = rec[11];
             cc = rec[12];
             ff = rec[13];
+        } else if (a.mode == 2) {
+            // isotropic elasticity, block (comp_i, comp_k): K_jl = c_{i j k l} with
+            // c_ijkl = lambda d_ij d_kl + mu (d_ik d_jl + d_il d_jk) (section 5.1)
+            const double E = rec[0], nu = rec[1];
+            const double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), mu = E / (2.0 * (1.0 + nu));
+            const int ci = a.comp_i, ck = a.comp_k;
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int s = 0; s < 3; ++s)
+                    K[r][s] = lam * (r == ci && s == ck) + mu * ((ci == ck && r == s) + (r == ck && s == ci));
+            bv[0] = bv[1] = bv[2] = 0.0;
+            cc = 0.0;
+            ff = rec[2 + ci];
         } else {
             const double *g = reinterpret_cast<const double *>(Dr);
             const double lam0 = exp10(g[0]), lam1 = exp10(g[1]), lam2 = exp10(g[2]);
@@ -1193,7 +1210,7 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
 #pragma unroll
             for (int q3 = 0; q3 < N; ++q3) sum += s_ld64[(q3 * N + c_) * 2] * t2[N * N * q3];
             const int64_t e = element_id(elist, e0 + el);
-            const int64_t base = a.b_off ? a.b_off[e] : e * (int64_t)NS;
+            const int64_t base = a.b_off ? a.b_off[e] : a.b_base + e * a.b_stride;
             outb[base + r] = (OT)sum;
         }
         __syncthreads();  // the temporaries overlay the staging area below
@@ -1226,7 +1243,7 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
         OT *stage = reinterpret_cast<OT *>(smem + S::off_D) + (size_t)wave * S::WIMG;
         if (el < neg) {
             const int64_t e = element_id(elist, e0 + el);
-            OT *dst0 = outA + (a.a_off ? a.a_off[e] : e * (int64_t)NS * NS);
+            OT *dst0 = outA + (a.a_off ? a.a_off[e] : a.a_base + e * a.a_stride);
             const float us = S::SPLIT ? a.row_scale_inv / split_scale(s_dmax[el], a.c_bound)
                                       : a.row_scale_inv;
 #pragma unroll
@@ -1271,7 +1288,7 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
                 const int el = col / S::NSP, jj = col % S::NSP;
                 if (jj >= NS || el >= neg) continue;
                 const int64_t e = element_id(elist, e0 + el);
-                OT *dst = outA + (a.a_off ? a.a_off[e] : e * (int64_t)NS * NS) + (int64_t)r0 * NS;
+                OT *dst = outA + (a.a_off ? a.a_off[e] : a.a_base + e * a.a_stride) + (int64_t)r0 * NS;
                 OT *img = s_img + el * S::WIMG + img_shift(dst);
                 const float us = S::SPLIT ? a.row_scale_inv / split_scale(s_dmax[el], a.c_bound)
                                           : a.row_scale_inv;
@@ -1285,7 +1302,7 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
             __syncthreads();
             for (int el = 0; el < neg; ++el) {
                 const int64_t e = element_id(elist, e0 + el);
-                OT *dst = outA + (a.a_off ? a.a_off[e] : e * (int64_t)NS * NS) + (int64_t)r0 * NS;
+                OT *dst = outA + (a.a_off ? a.a_off[e] : a.a_base + e * a.a_stride) + (int64_t)r0 * NS;
                 copy_out(dst, s_img + el * S::WIMG + img_shift(dst), nrow * NS, tid, NT);
             }
             __syncthreads();
@@ -1302,7 +1319,7 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
             const int el = col / S::NSP, jj = col % S::NSP;
             if (jj >= NS || el >= neg) continue;
             const int64_t e = element_id(elist, e0 + el);
-            OT *img = s_out + el * S::IMG + img_shift(outA + (a.a_off ? a.a_off[e] : e * (int64_t)NS * NS));
+            OT *img = s_out + el * S::IMG + img_shift(outA + (a.a_off ? a.a_off[e] : a.a_base + e * a.a_stride));
             const float us = S::SPLIT ? a.row_scale_inv / split_scale(s_dmax[el], a.c_bound)
                                       : a.row_scale_inv;
 #pragma unroll
@@ -1321,7 +1338,7 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
         __syncthreads();
         for (int el = 0; el < neg; ++el) {
             const int64_t e = element_id(elist, e0 + el);
-            OT *dst = outA + (a.a_off ? a.a_off[e] : e * (int64_t)NS * NS);
+            OT *dst = outA + (a.a_off ? a.a_off[e] : a.a_base + e * a.a_stride);
             copy_out(dst, s_out + el * S::IMG + img_shift(dst), NS * NS, tid, NT);
         }
     } else {
@@ -1333,7 +1350,7 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
             const int el = col / S::NSP, jj = col % S::NSP;
             if (jj >= NS || el >= neg) continue;
             const int64_t e = element_id(elist, e0 + el);
-            const int64_t base = a.a_off ? a.a_off[e] : e * (int64_t)NS * NS;
+            const int64_t base = a.a_off ? a.a_off[e] : a.a_base + e * a.a_stride;
             const float us = S::SPLIT ? a.row_scale_inv / split_scale(s_dmax[el], a.c_bound)
                                       : a.row_scale_inv;
 #pragma unroll
@@ -1373,7 +1390,7 @@ __device__ inline void run_items(const KArgs &a, int64_t wi, const int64_t strid
     const int64_t total = ((nel + S::EG - 1) / S::EG) * S::RT * S::CT;
     if (wi >= total) return;
     const int tid = threadIdx.x;
-    const int reclen = a.mode == 0 ? 14 : 10;
+    const int reclen = a.mode == 0 ? 14 : (a.mode == 1 ? 10 : 5);
 
     // ---- per-workgroup constants: tables, field descriptor, point rows, resident row table ----
     double *s_fld = reinterpret_cast<double *>(smem + S::off_fld);

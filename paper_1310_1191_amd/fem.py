@@ -24,7 +24,7 @@ FEM_EWORKSPACE = -7
 FP64, FP32, BF16, SPLIT_BF16, SPLIT_FP16 = 0, 1, 2, 3, 4
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "split_bf16": SPLIT_BF16,
               "split_fp16": SPLIT_FP16}
-ELEMENT, FIELD = 0, 1
+ELEMENT, FIELD, ELASTIC = 0, 1, 2
 
 
 class fem_coeffs(ctypes.Structure):
@@ -255,7 +255,8 @@ def out_dtype(precision):
 
 def integrate(geom, elem, p: int, precision="split_bf16", mode: int = ELEMENT, field=None,
               out_A=None, out_b=None, status=None, with_b: bool = True, stream=None):
-    """Uniform degree p: returns (A [nel, Ns, Ns], b [nel, Ns] or None) on the device."""
+    """Uniform degree p: returns (A [nel, Ns, Ns], b [nel, Ns] or None) on the device; for
+    mode ELASTIC (elem [nel, 5] = E, nu, f1, f2, f3) A is [nel, 3, 3, Ns, Ns], b [nel, 3, Ns]."""
     torch = _torch()
     fem_init(geom.device.index or 0)
     nel = geom.shape[0]
@@ -264,10 +265,11 @@ def integrate(geom, elem, p: int, precision="split_bf16", mode: int = ELEMENT, f
     _check(geom, torch.float64, "geom")
     _check(elem, torch.float64, "elem")
     _check(field, torch.float64, "field")
+    ashape, bshape = ((nel, 3, 3, ns, ns), (nel, 3, ns)) if mode == ELASTIC else ((nel, ns, ns), (nel, ns))
     if out_A is None:
-        out_A = torch.empty((nel, ns, ns), dtype=dt, device=geom.device)
+        out_A = torch.empty(ashape, dtype=dt, device=geom.device)
     if out_b is None and with_b:
-        out_b = torch.empty((nel, ns), dtype=dt, device=geom.device)
+        out_b = torch.empty(bshape, dtype=dt, device=geom.device)
     c = make_coeffs(precision, mode, elem, field=field, status=status)
     rc = fem_integrate(nel, p, _ptr(geom), c, _ptr(out_A), _ptr(out_b), _stream(stream))
     if rc != FEM_OK:

@@ -117,6 +117,16 @@ def field_descriptor(rng: np.random.Generator) -> np.ndarray:
     return d.reshape(-1).copy()
 
 
+def elastic_coeffs(nel: int, rng: np.random.Generator) -> np.ndarray:
+    """Per-element material data of the elastostatics model problem (section 5.1): Young modulus
+    E ~ U[1, 10], Poisson ratio nu ~ U[0.2, 0.4], body force f ~ U[-1, 1]^3. [nel, 5]."""
+    rec = np.empty((nel, 5))
+    rec[:, 0] = rng.uniform(1.0, 10.0, nel)
+    rec[:, 1] = rng.uniform(0.2, 0.4, nel)
+    rec[:, 2:5] = rng.uniform(-1.0, 1.0, (nel, 3))
+    return rec
+
+
 def phase_shift(seed: int, step: int) -> np.ndarray:
     """The phase increment delta_t ~ U[0, 2 pi)^{7x5} of time step ``step`` (>= 1)."""
     return np.random.default_rng([seed, step]).uniform(0.0, 2.0 * np.pi, size=(7, 5))

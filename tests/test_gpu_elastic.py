@@ -1,0 +1,83 @@
+"""GPU parity for the vector model problem (linear elastostatics, section 5.1) against the FP64
+oracle: every degree, the FP64, FP32 and split-FP16 paths, element by element on jittered
+meshes (several elements and a ragged tail where the oracle is fast enough)."""
+import numpy as np
+import pytest
+
+from gpu_cases import TOL_A, TOL_B, log, rel_fro, rel_vec, to_dev
+from paper_1310_1191_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = {1: (5, 4, 3), 2: (4, 3, 2), 3: (3, 2, 2), 4: (2, 2, 1), 5: (2, 1, 1), 6: (1, 1, 1),
+         7: (1, 1, 1)}
+
+
+@pytest.fixture(scope="module")
+def fem():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    from paper_1310_1191_amd import fem as F
+    F.fem_init(0)
+    return F
+
+
+_cache = {}
+
+
+def elastic_case(p):
+    if p not in _cache:
+        import oracle
+        rng = np.random.default_rng(60 + p)
+        nodes = synth.node_grid(*GRIDS[p], 0.15, rng)
+        geom = synth.element_vertices(nodes)
+        coef = synth.elastic_coeffs(geom.shape[0], rng)
+        A, b, fl = oracle.integrate_elastic(geom, coef, p)
+        _cache[p] = (geom, coef, A, b, fl)
+    return _cache[p]
+
+
+def full(A):
+    """[nel, 3, 3, Ns, Ns] -> [nel, 3 Ns, 3 Ns] indexed ((i, s), (k, r))."""
+    nel, _, _, ns, _ = A.shape
+    return A.transpose(0, 1, 3, 2, 4).reshape(nel, 3 * ns, 3 * ns)
+
+
+@pytest.mark.parametrize("p", range(1, 8))
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "split_fp16"])
+def test_elastic_parity(fem, p, prec):
+    import torch
+    geom, coef, A_ref, b_ref, fl = elastic_case(p)
+    g, c = to_dev(geom, coef)
+    status = torch.zeros(2, dtype=torch.int32, device="cuda")
+    A, b = fem.integrate(g, c, p, precision=prec, mode=fem.ELASTIC, status=status)
+    torch.cuda.synchronize()
+    A = A.double().cpu().numpy()
+    b = b.double().cpu().numpy()
+    ea = rel_fro(full(A), full(A_ref))
+    eb = rel_vec(b.reshape(len(b), -1), b_ref.reshape(len(b_ref), -1))
+    log(f"[elastic] p={p} prec={prec} nel={geom.shape[0]} errA max={ea.max():.3e} errb max={eb.max():.3e}")
+    assert status.cpu().tolist() == [0, 0]
+    assert ea.max() <= TOL_A[prec] and eb.max() <= TOL_B[prec]
+
+
+def test_elastic_status_counted_once(fem):
+    """An inverted element is counted once, not once per block."""
+    import torch
+    geom, coef, *_ = elastic_case(2)
+    g = geom.copy()
+    g[1] = g[1][[1, 0, 3, 2, 5, 4, 7, 6]]          # mirror element 1: detJ < 0
+    gd, cd = to_dev(g, coef)
+    status = torch.zeros(2, dtype=torch.int32, device="cuda")
+    fem.integrate(gd, cd, 2, precision="fp64", mode=fem.ELASTIC, status=status)
+    torch.cuda.synchronize()
+    assert status.cpu().tolist()[0] == 1
+
+
+def test_elastic_mixed_degree_is_rejected(fem):
+    import torch
+    geom, coef, *_ = elastic_case(1)
+    g, c = to_dev(geom, coef)
+    cc = fem.make_coeffs("fp64", fem.ELASTIC, c)
+    out = torch.empty(1, device="cuda")
+    assert fem.fem_integrate(geom.shape[0], 0, g.data_ptr(), cc, out.data_ptr(), None, None) != fem.FEM_OK
