@@ -121,11 +121,13 @@ def main():
     ap.add_argument("--precision", default="split_fp16")
     ap.add_argument("--compare", default="fp32", help="second path timed for comparison ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="plain", choices=["plain", "high", "mixed", "timestep", "poisson"],
+    ap.add_argument("--workload", default="plain",
+                    choices=["plain", "high", "mixed", "timestep", "poisson", "elasticity"],
                     help="plain: p = 2, 3, 4 at scale (the headline); high: p = 5, 6, 7 in every "
                          "precision; mixed: 200000 elements of degrees 1..7 with coefficient fields, "
                          "one launch against per-degree launches; timestep: 50 graph-replayed steps "
-                         "of 100000 mixed-degree elements; poisson: p = 1")
+                         "of 100000 mixed-degree elements; poisson: p = 1; elasticity: the vector "
+                         "model problem (linear elastostatics) for p = 2..7")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain elementwise copy y = -x of MIB MiB three times (the "
                          "known-size kernel that calibrates HBM byte counters)")
@@ -145,7 +147,8 @@ def main():
 
     if args.workload != "plain":
         line = {"high": bench_high, "mixed": bench_mixed, "timestep": bench_timestep,
-                "poisson": bench_poisson}[args.workload](args, torch, fem, synth, dev)
+                "poisson": bench_poisson, "elasticity": bench_elasticity}[args.workload](
+            args, torch, fem, synth, dev)
         print(json.dumps(line), flush=True)
         return
 
@@ -546,6 +549,53 @@ def bench_poisson(args, torch, fem, synth, dev):
             "config": {"workload": "p=1 Poisson, 16^3 (4096 elements) and 128^3 (2097152 elements) "
                                    "jittered grids"},
             "results": res}
+
+
+def bench_elasticity(args, torch, fem, synth, dev):
+    """Linear elastostatics (3 components, isotropic material per element, the paper's model
+    problem) on the plain-method grids for p = 2, 3, 4 and the high-order grids for p = 5, 6, 7;
+    output 9 Ns^2 + 3 Ns per element; sampled errors against the FP64 oracle."""
+    import oracle
+    grids = {2: (64, 64, 64), 3: (64, 64, 32), 4: (64, 32, 32), 5: (32, 32, 16), 6: (32, 16, 16),
+             7: (16, 16, 16)}
+    out = {}
+    for p, grid in grids.items():
+        rng = np.random.default_rng(70 + p)
+        nodes = synth.node_grid(*grid, 0.15, rng)
+        geom = synth.element_vertices(nodes)
+        coef = synth.elastic_coeffs(geom.shape[0], rng)
+        nel = geom.shape[0]
+        g, c = torch.from_numpy(geom).to(dev), torch.from_numpy(coef).to(dev)
+        idx = np.random.default_rng(p).choice(nel, 4 if p <= 5 else 2, replace=False)
+        Aref, _, _ = oracle.integrate_elastic(geom[idx], coef[idx], p, threads=oracle_threads(),
+                                              with_b=False)
+        ns = (p + 1) ** 3
+        res = {"nel": nel}
+        for prec in ["split_fp16", "fp32"]:
+            A = torch.empty((nel, 3, 3, ns, ns), dtype=fem.out_dtype(prec), device=dev)
+            b = torch.empty((nel, 3, ns), dtype=fem.out_dtype(prec), device=dev)
+            ms = time_calls(torch, lambda: fem.integrate(g, c, p, precision=prec, mode=fem.ELASTIC,
+                                                         out_A=A, out_b=b), max(3, args.steps // 5), 1)
+            Ag = A[torch.from_numpy(idx).to(dev)].double().cpu().numpy()
+            errs = [rel_fro(Ag[k], Aref[k]) for k in range(idx.size)]
+            fl = 9 * flops_per_element(p) * nel / (ms * 1e-3) / 1e12
+            gbs = (192 + 40 + 4 * (9 * ns * ns + 3 * ns)) * nel / (ms * 1e-3) / 1e9
+            res[prec] = {"ms": round(ms, 3), "el_per_s": nel / (ms * 1e-3), "tflops": round(fl, 2),
+                         "frac_peak": round(fl / PEAK_TFLOPS[prec], 4), "gbs": round(gbs, 1),
+                         "max_rel_err_sample": max(errs)}
+            log(f"[bench] elasticity p={p} {prec}: {ms:.3f} ms, {fl:.1f} TFLOP/s, max err {max(errs):.2e}")
+            del A, b
+            torch.cuda.empty_cache()
+        out[str(p)] = res
+    tot_el = sum(out[k]["nel"] for k in out)
+    tot_ms = sum(out[k]["split_fp16"]["ms"] for k in out)
+    return {"metric": "element matrices/s (split-precision MFMA, <= 1e-6 relative error)",
+            "value": tot_el / (tot_ms * 1e-3), "unit": "element matrices/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f16x3->f32", "data": "synthetic",
+            "config": {"workload": "linear elastostatics hex p=2..7 (3 components, E ~ U[1,10], "
+                                   "nu ~ U[0.2,0.4] per element) on the plain and high-order grids",
+                       "sample": "4 (p<=5) or 2 random elements per degree against the FP64 oracle"},
+            "per_degree": out}
 
 
 if __name__ == "__main__":
