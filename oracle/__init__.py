@@ -58,6 +58,16 @@ def _load():
     lib.oracle_integrate_elastic.argtypes = [
         ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+    lib.oracle_jacobian_terms.argtypes = [
+        ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_int]
+    lib.oracle_integrate_nojac.argtypes = [
+        ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+    lib.oracle_integrate_elastic_nojac.argtypes = [
+        ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
     lib.oracle_max_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -175,4 +185,85 @@ def integrate_elastic(geom, coef, p: int, threads: int = 0, with_b: bool = True)
                                          threads)
     if rc != 0:
         raise ValueError("oracle_integrate_elastic: bad arguments")
+    return A, b, flags
+
+
+def jacobian_terms(geom, p: int | None = None, degree=None, threads: int = 0):
+    """Per-point Jacobian terms of the NOJAC variant (section 4): [.., 10] = detJ, then J^{-1}
+    row-major, for q = q1 + n q2 + n^2 q3. Uniform p: shape [nel, Ns, 10]; mixed degree: the
+    records packed by the b_off scan, shape [sum Ns, 10]."""
+    geom = np.ascontiguousarray(geom, dtype=np.float64)
+    nel = geom.shape[0]
+    assert geom.shape[1:] == (8, 3)
+    lib = _load()
+    if degree is None:
+        ns = (p + 1) ** 3 if p is not None and 1 <= p <= 7 else 1
+        out = np.zeros((nel, ns, 10))
+        rc = lib.oracle_jacobian_terms(nel, -1 if p is None else p, None, None, _vp(geom), _vp(out),
+                                       threads)
+    else:
+        deg = np.ascontiguousarray(degree, dtype=np.int8)
+        _, b_off = mixed_offsets(deg)
+        out = np.zeros((int(b_off[-1]), 10))
+        rc = lib.oracle_jacobian_terms(nel, 0, _vp(deg), _vp(b_off), _vp(geom), _vp(out), threads)
+    if rc != 0:
+        raise ValueError("oracle_jacobian_terms: bad arguments")
+    return out
+
+
+def integrate_nojac(jac, coef, p: int | None = None, degree=None, mode: int = ELEMENT,
+                    geom=None, field=None, threads: int = 0, with_b: bool = True):
+    """``integrate`` with the Jacobian terms read from ``jac`` (layout of ``jacobian_terms``)
+    instead of computed from vertices; ``geom`` is needed only in FIELD mode (for x_q)."""
+    jac = np.ascontiguousarray(jac, dtype=np.float64)
+    coef = np.ascontiguousarray(coef, dtype=np.float64)
+    nel = coef.shape[0]
+    rec = 14 if mode == ELEMENT else 10
+    assert coef.shape == (nel, rec) and jac.shape[-1] == 10
+    if geom is not None:
+        geom = np.ascontiguousarray(geom, dtype=np.float64)
+        assert geom.shape == (nel, 8, 3)
+    fld = None
+    if mode == FIELD:
+        fld = np.ascontiguousarray(field, dtype=np.float64).reshape(-1)
+        assert fld.size == 175
+    flags = np.zeros(nel, dtype=np.int32)
+    lib = _load()
+    if degree is None:
+        ns = (p + 1) ** 3 if p is not None and 1 <= p <= 7 else 1
+        assert jac.size == nel * ns * 10
+        A = np.zeros((nel, ns, ns))
+        b = np.zeros((nel, ns)) if with_b else None
+        rc = lib.oracle_integrate_nojac(nel, -1 if p is None else p, None, _vp(jac), _vp(geom), mode,
+                                        _vp(coef), _vp(fld), None, None, _vp(A), _vp(b), _vp(flags),
+                                        threads)
+        if rc != 0:
+            raise ValueError("oracle_integrate_nojac: bad arguments")
+        return A, b, flags
+    deg = np.ascontiguousarray(degree, dtype=np.int8)
+    a_off, b_off = mixed_offsets(deg)
+    assert jac.size == int(b_off[-1]) * 10
+    A = np.zeros(int(a_off[-1]))
+    b = np.zeros(int(b_off[-1])) if with_b else None
+    rc = lib.oracle_integrate_nojac(nel, 0, _vp(deg), _vp(jac), _vp(geom), mode, _vp(coef), _vp(fld),
+                                    _vp(a_off), _vp(b_off), _vp(A), _vp(b), _vp(flags), threads)
+    if rc != 0:
+        raise ValueError("oracle_integrate_nojac: bad arguments")
+    return A, b, flags, a_off, b_off
+
+
+def integrate_elastic_nojac(jac, coef, p: int, threads: int = 0, with_b: bool = True):
+    """``integrate_elastic`` with the Jacobian terms read from ``jac`` [nel, Ns, 10]."""
+    jac = np.ascontiguousarray(jac, dtype=np.float64)
+    coef = np.ascontiguousarray(coef, dtype=np.float64)
+    nel = coef.shape[0]
+    ns = (p + 1) ** 3 if 1 <= p <= 7 else 1
+    assert coef.shape == (nel, 5) and jac.size == nel * ns * 10
+    A = np.zeros((nel, 3, 3, ns, ns))
+    b = np.zeros((nel, 3, ns)) if with_b else None
+    flags = np.zeros(nel, dtype=np.int32)
+    rc = _load().oracle_integrate_elastic_nojac(nel, p, _vp(jac), _vp(coef), _vp(A), _vp(b),
+                                               _vp(flags), threads)
+    if rc != 0:
+        raise ValueError("oracle_integrate_elastic_nojac: bad arguments")
     return A, b, flags

@@ -165,12 +165,80 @@ static void point_coefficients(int mode, const double *rec, const double *field,
     *f = rec[9];
 }
 
+/* The trilinear map at xi: position x, Jacobian J[a][b] = dx_a / dxi_b, determinant and inverse
+ * (adjugate / det). X is the element's [8][3] vertex array. */
+static void trilinear_jacobian(const double *X, const double *xi, double *x, double J[3][3],
+                               double *det, double Ji[3][3])
+{
+    for (int a = 0; a < 3; ++a) {
+        x[a] = 0.0;
+        for (int b = 0; b < 3; ++b)
+            J[a][b] = 0.0;
+    }
+    for (int v = 0; v < 8; ++v) {
+        const double s1 = (v & 1) ? 1.0 : -1.0;
+        const double s2 = (v & 2) ? 1.0 : -1.0;
+        const double s3 = (v & 4) ? 1.0 : -1.0;
+        const double f1 = 1.0 + s1 * xi[0], f2 = 1.0 + s2 * xi[1], f3 = 1.0 + s3 * xi[2];
+        const double Nv = f1 * f2 * f3 / 8.0;
+        const double dN[3] = {s1 * f2 * f3 / 8.0, f1 * s2 * f3 / 8.0, f1 * f2 * s3 / 8.0};
+        for (int a = 0; a < 3; ++a) {
+            x[a] += X[v * 3 + a] * Nv;
+            for (int b = 0; b < 3; ++b)
+                J[a][b] += X[v * 3 + a] * dN[b];
+        }
+    }
+    const double d = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                     J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                     J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / d;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / d;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / d;
+    Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / d;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / d;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / d;
+    Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / d;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / d;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / d;
+    *det = d;
+}
+
+/* The Jacobian terms (detJ and J^{-1}) at point q = q1 + n q2 + n^2 q3 with coordinates xi:
+ * computed from the vertices X when jt == NULL, else read from jt[q][0] (detJ) and jt[q][1..9]
+ * (J^{-1} row-major). xq receives the physical point when X is given (zeros otherwise).
+ * Returns ORACLE_FLAG_* bits for the point. */
+static int point_jacobian(const double *X, const double *jt, int q, const double *xi, double *xq,
+                          double *det, double Ji[3][3])
+{
+    int flags = 0;
+    double J[3][3];
+    xq[0] = xq[1] = xq[2] = 0.0;
+    if (X)
+        trilinear_jacobian(X, xi, xq, J, det, Ji);
+    if (jt) {
+        const double *r = jt + (size_t)q * 10;
+        *det = r[0];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                Ji[a][b] = r[1 + 3 * a + b];
+        for (int t = 0; t < 10; ++t)
+            if (!isfinite(r[t]))
+                flags |= ORACLE_FLAG_NONFINITE;
+    }
+    if (!(*det > 0.0))
+        flags |= ORACLE_FLAG_DETJ;
+    return flags;
+}
+
 /* One element, following Algorithm 2 of section 2: read coefficients and geometry, zero A^e,
  * then for each quadrature point read the reference shape functions, compute the Jacobian, its
  * determinant and inverse, the physical derivatives psi, the point coefficients, and update every
- * (i, j) entry. Returns ORACLE_FLAG_* bits. */
-static int integrate_one(int p, const double *X, int mode, const double *rec, const double *field,
-                         double *A, double *bvec)
+ * (i, j) entry. Returns ORACLE_FLAG_* bits.
+ * With jt != NULL (the NOJAC variant of section 4) the determinant and inverse at point q are
+ * read from jt[q][0] and jt[q][1..9] (J^{-1} row-major) instead; X then only supplies the
+ * physical point x_q for FIELD mode and may be NULL otherwise. */
+static int integrate_one(int p, const double *X, const double *jt, int mode, const double *rec,
+                         const double *field, double *A, double *bvec)
 {
     const int n = p + 1;
     const int ns = n * n * n;
@@ -184,9 +252,10 @@ static int integrate_one(int p, const double *X, int mode, const double *rec, co
     for (int q = 0; q < n; ++q)
         oracle_lagrange(n, nodes, gx[q], L[q], D[q]);
 
-    for (int t = 0; t < 24; ++t)
-        if (!isfinite(X[t]))
-            flags |= ORACLE_FLAG_NONFINITE;
+    if (X)
+        for (int t = 0; t < 24; ++t)
+            if (!isfinite(X[t]))
+                flags |= ORACLE_FLAG_NONFINITE;
 
     memset(A, 0, sizeof(double) * (size_t)ns * ns);
     if (bvec)
@@ -209,36 +278,9 @@ static int integrate_one(int p, const double *X, int mode, const double *rec, co
                             phi[i][3] = L[q1][a] * L[q2][b] * D[q3][c];
                         }
 
-                /* Jacobian of the trilinear map, J[a][b] = dx_a / dxi_b */
-                double J[3][3] = {{0}}, xq[3] = {0, 0, 0};
-                for (int v = 0; v < 8; ++v) {
-                    const double s1 = (v & 1) ? 1.0 : -1.0;
-                    const double s2 = (v & 2) ? 1.0 : -1.0;
-                    const double s3 = (v & 4) ? 1.0 : -1.0;
-                    const double f1 = 1.0 + s1 * xi[0], f2 = 1.0 + s2 * xi[1], f3 = 1.0 + s3 * xi[2];
-                    const double Nv = f1 * f2 * f3 / 8.0;
-                    const double dN[3] = {s1 * f2 * f3 / 8.0, f1 * s2 * f3 / 8.0, f1 * f2 * s3 / 8.0};
-                    for (int a = 0; a < 3; ++a) {
-                        xq[a] += X[v * 3 + a] * Nv;
-                        for (int b = 0; b < 3; ++b)
-                            J[a][b] += X[v * 3 + a] * dN[b];
-                    }
-                }
-                const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
-                                   J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
-                                   J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-                if (!(det > 0.0))
-                    flags |= ORACLE_FLAG_DETJ;
-                double Ji[3][3]; /* inverse = adjugate / det */
-                Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
-                Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
-                Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
-                Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
-                Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
-                Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
-                Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
-                Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
-                Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+                /* Jacobian terms: computed from the trilinear map of the vertices, or read */
+                double Ji[3][3], det, xq[3];
+                flags |= point_jacobian(X, jt, q1 + n * q2 + n * n * q3, xi, xq, &det, Ji);
 
                 /* physical derivatives psi^Q[i_Q]: d_k phi = sum_m (J^{-1})_{mk} d phi / d xi_m */
                 for (int i = 0; i < ns; ++i) {
@@ -275,23 +317,24 @@ static int integrate_one(int p, const double *X, int mode, const double *rec, co
     return flags;
 }
 
-int oracle_integrate(int64_t nel, int p, const int8_t *degree, const double *geom, int mode,
-                     const double *coef, const double *field, const int64_t *a_off,
-                     const int64_t *b_off, double *out_A, double *out_b, int32_t *flags,
-                     int nthreads)
+/* Element e's Jacobian terms start at jac + 10 * (b_off ? b_off[e] : e * Nq) (Nq = Ns). */
+static int integrate_all(int64_t nel, int p, const int8_t *degree, const double *geom,
+                         const double *jac, int mode, const double *coef, const double *field,
+                         const int64_t *a_off, const int64_t *b_off, double *out_A, double *out_b,
+                         int32_t *flags, int nthreads)
 {
     if (nel < 0)
         return -1;
     if (nel == 0)
         return 0;
-    if (!geom || !coef || !out_A)
+    if (!coef || !out_A || (!geom && !jac))
         return -1;
     if (mode != ORACLE_COEF_ELEMENT && mode != ORACLE_COEF_FIELD)
         return -1;
-    if (mode == ORACLE_COEF_FIELD && !field)
+    if (mode == ORACLE_COEF_FIELD && (!field || !geom))
         return -1;
     if (degree) {
-        if (!a_off || (out_b && !b_off))
+        if (!a_off || ((out_b || jac) && !b_off))
             return -1;
         for (int64_t e = 0; e < nel; ++e)
             if (degree[e] < 1 || degree[e] > 7)
@@ -311,10 +354,71 @@ int oracle_integrate(int64_t nel, int p, const int8_t *degree, const double *geo
         const int64_t ns = (int64_t)(pe + 1) * (pe + 1) * (pe + 1);
         const int64_t ao = a_off ? a_off[e] : e * ns * ns;
         const int64_t bo = b_off ? b_off[e] : e * ns;
-        int fl = integrate_one(pe, geom + e * 24, mode, coef + e * rec_len, field, out_A + ao,
-                               out_b ? out_b + bo : NULL);
+        int fl = integrate_one(pe, geom ? geom + e * 24 : NULL, jac ? jac + 10 * bo : NULL, mode,
+                               coef + e * rec_len, field, out_A + ao, out_b ? out_b + bo : NULL);
         if (flags)
             flags[e] = fl;
+    }
+    return 0;
+}
+
+int oracle_integrate(int64_t nel, int p, const int8_t *degree, const double *geom, int mode,
+                     const double *coef, const double *field, const int64_t *a_off,
+                     const int64_t *b_off, double *out_A, double *out_b, int32_t *flags,
+                     int nthreads)
+{
+    if (nel > 0 && !geom)
+        return -1;
+    return integrate_all(nel, p, degree, geom, NULL, mode, coef, field, a_off, b_off, out_A, out_b,
+                         flags, nthreads);
+}
+
+int oracle_integrate_nojac(int64_t nel, int p, const int8_t *degree, const double *jac,
+                           const double *geom, int mode, const double *coef, const double *field,
+                           const int64_t *a_off, const int64_t *b_off, double *out_A,
+                           double *out_b, int32_t *flags, int nthreads)
+{
+    if (nel > 0 && !jac)
+        return -1;
+    return integrate_all(nel, p, degree, geom, jac, mode, coef, field, a_off, b_off, out_A, out_b,
+                         flags, nthreads);
+}
+
+int oracle_jacobian_terms(int64_t nel, int p, const int8_t *degree, const int64_t *b_off,
+                          const double *geom, double *out, int nthreads)
+{
+    if (nel < 0)
+        return -1;
+    if (nel == 0)
+        return 0;
+    if (!geom || !out || (degree && !b_off) || (!degree && (p < 1 || p > 7)))
+        return -1;
+    if (degree)
+        for (int64_t e = 0; e < nel; ++e)
+            if (degree[e] < 1 || degree[e] > 7)
+                return -1;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t e = 0; e < nel; ++e) {
+        const int n = (degree ? degree[e] : p) + 1;
+        const int64_t bo = degree ? b_off[e] : e * (int64_t)n * n * n;
+        double gx[MAX_N], gw[MAX_N];
+        oracle_gauss_legendre(n, gx, gw);
+        for (int q3 = 0; q3 < n; ++q3)
+            for (int q2 = 0; q2 < n; ++q2)
+                for (int q1 = 0; q1 < n; ++q1) {
+                    const double xi[3] = {gx[q1], gx[q2], gx[q3]};
+                    double x[3], J[3][3], Ji[3][3], det;
+                    trilinear_jacobian(geom + e * 24, xi, x, J, &det, Ji);
+                    double *r = out + 10 * (bo + q1 + n * q2 + n * n * q3);
+                    r[0] = det;
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b)
+                            r[1 + 3 * a + b] = Ji[a][b];
+                }
     }
     return 0;
 }
@@ -332,7 +436,8 @@ int oracle_integrate(int64_t nel, int p, const int8_t *degree, const double *geo
  *   c_ijkl = lambda delta_ij delta_kl + mu (delta_ik delta_jl + delta_il delta_jk).
  * Load vector (body force f, constant per element): b[(i,s)] = sum_q f_i phi_s detJ w_q.
  * ------------------------------------------------------------------------------------------- */
-static int integrate_elastic_one(int p, const double *X, const double *rec, double *A, double *bvec)
+static int integrate_elastic_one(int p, const double *X, const double *jt, const double *rec,
+                                 double *A, double *bvec)
 {
     const int n = p + 1;
     const int ns = n * n * n;
@@ -345,9 +450,10 @@ static int integrate_elastic_one(int p, const double *X, const double *rec, doub
     oracle_gll_nodes(p, nodes);
     for (int q = 0; q < n; ++q)
         oracle_lagrange(n, nodes, gx[q], L[q], D[q]);
-    for (int t = 0; t < 24; ++t)
-        if (!isfinite(X[t]))
-            flags |= ORACLE_FLAG_NONFINITE;
+    if (X)
+        for (int t = 0; t < 24; ++t)
+            if (!isfinite(X[t]))
+                flags |= ORACLE_FLAG_NONFINITE;
 
     const double E = rec[0], nu = rec[1];
     const double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
@@ -377,32 +483,8 @@ static int integrate_elastic_one(int p, const double *X, const double *rec, doub
                             phi[r][2] = L[q1][aa] * D[q2][bb] * L[q3][cc];
                             phi[r][3] = L[q1][aa] * L[q2][bb] * D[q3][cc];
                         }
-                double J[3][3] = {{0}};
-                for (int v = 0; v < 8; ++v) {
-                    const double s1 = (v & 1) ? 1.0 : -1.0;
-                    const double s2 = (v & 2) ? 1.0 : -1.0;
-                    const double s3 = (v & 4) ? 1.0 : -1.0;
-                    const double f1 = 1.0 + s1 * xi[0], f2 = 1.0 + s2 * xi[1], f3 = 1.0 + s3 * xi[2];
-                    const double dN[3] = {s1 * f2 * f3 / 8.0, f1 * s2 * f3 / 8.0, f1 * f2 * s3 / 8.0};
-                    for (int a = 0; a < 3; ++a)
-                        for (int b = 0; b < 3; ++b)
-                            J[a][b] += X[v * 3 + a] * dN[b];
-                }
-                const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
-                                   J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
-                                   J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-                if (!(det > 0.0))
-                    flags |= ORACLE_FLAG_DETJ;
-                double Ji[3][3];
-                Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
-                Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
-                Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
-                Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
-                Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
-                Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
-                Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
-                Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
-                Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+                double Ji[3][3], det, xq[3];
+                flags |= point_jacobian(X, jt, q1 + n * q2 + n * n * q3, xi, xq, &det, Ji);
                 /* d phi / d x_l = sum_m (d phi / d xi_m)(d xi_m / d x_l), a column of J^{-1} */
                 for (int r = 0; r < ns; ++r) {
                     psi[r][0] = phi[r][0];
@@ -433,14 +515,15 @@ static int integrate_elastic_one(int p, const double *X, const double *rec, doub
     return flags;
 }
 
-int oracle_integrate_elastic(int64_t nel, int p, const double *geom, const double *coef,
-                             double *out_A, double *out_b, int32_t *flags, int nthreads)
+static int integrate_elastic_all(int64_t nel, int p, const double *geom, const double *jac,
+                                 const double *coef, double *out_A, double *out_b, int32_t *flags,
+                                 int nthreads)
 {
     if (nel < 0)
         return -1;
     if (nel == 0)
         return 0;
-    if (!geom || !coef || !out_A || p < 1 || p > 7)
+    if ((!geom && !jac) || !coef || !out_A || p < 1 || p > 7)
         return -1;
     const int64_t ns = (int64_t)(p + 1) * (p + 1) * (p + 1);
 #ifdef _OPENMP
@@ -449,12 +532,29 @@ int oracle_integrate_elastic(int64_t nel, int p, const double *geom, const doubl
 #pragma omp parallel for schedule(dynamic, 1)
 #endif
     for (int64_t e = 0; e < nel; ++e) {
-        int fl = integrate_elastic_one(p, geom + e * 24, coef + e * 5, out_A + e * 9 * ns * ns,
+        int fl = integrate_elastic_one(p, geom ? geom + e * 24 : NULL, jac ? jac + e * 10 * ns : NULL,
+                                       coef + e * 5, out_A + e * 9 * ns * ns,
                                        out_b ? out_b + e * 3 * ns : NULL);
         if (flags)
             flags[e] = fl;
     }
     return 0;
+}
+
+int oracle_integrate_elastic(int64_t nel, int p, const double *geom, const double *coef,
+                             double *out_A, double *out_b, int32_t *flags, int nthreads)
+{
+    if (nel > 0 && !geom)
+        return -1;
+    return integrate_elastic_all(nel, p, geom, NULL, coef, out_A, out_b, flags, nthreads);
+}
+
+int oracle_integrate_elastic_nojac(int64_t nel, int p, const double *jac, const double *coef,
+                                   double *out_A, double *out_b, int32_t *flags, int nthreads)
+{
+    if (nel > 0 && !jac)
+        return -1;
+    return integrate_elastic_all(nel, p, NULL, jac, coef, out_A, out_b, flags, nthreads);
 }
 
 int oracle_max_threads(void)

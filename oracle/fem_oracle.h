@@ -83,6 +83,27 @@ int oracle_integrate(int64_t nel, int p, const int8_t *degree, const double *geo
 int oracle_integrate_elastic(int64_t nel, int p, const double *geom, const double *coef,
                              double *out_A, double *out_b, int32_t *flags, int nthreads);
 
+/* Jacobian terms of the NOJAC variant (section 4: the determinant and the 9 entries of the
+ * inverse Jacobian for every element and quadrature point, supplied instead of recomputed):
+ *   out[q][0] = detJ(xi_q), out[q][1 + 3a + b] = (J^{-1})[a][b], J[a][b] = dx_a / dxi_b, for
+ *   q = q1 + n q2 + n^2 q3 of the element's Gauss-Legendre rule. Element e's Nq = Ns records start
+ *   at out + 10 * (degree ? b_off[e] : e * Ns); degree == NULL selects the uniform p.
+ * Returns 0, or -1 on an argument error. */
+int oracle_jacobian_terms(int64_t nel, int p, const int8_t *degree, const int64_t *b_off,
+                          const double *geom, double *out, int nthreads);
+
+/* oracle_integrate with the Jacobian terms read from jac (layout of oracle_jacobian_terms;
+ * mixed degree then needs b_off even without out_b) instead of computed from the vertices.
+ * geom supplies x_q in FIELD mode and may be NULL in ELEMENT mode. */
+int oracle_integrate_nojac(int64_t nel, int p, const int8_t *degree, const double *jac,
+                           const double *geom, int mode, const double *coef, const double *field,
+                           const int64_t *a_off, const int64_t *b_off, double *out_A,
+                           double *out_b, int32_t *flags, int nthreads);
+
+/* oracle_integrate_elastic with the Jacobian terms read from jac ([nel][Ns][10]). */
+int oracle_integrate_elastic_nojac(int64_t nel, int p, const double *jac, const double *coef,
+                                   double *out_A, double *out_b, int32_t *flags, int nthreads);
+
 /* Number of OpenMP threads a call with nthreads = 0 uses. */
 int oracle_max_threads(void);
 
