@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define FEM_ABI_VERSION 1
+#define FEM_ABI_VERSION 2
 
 typedef enum {
     FEM_OK = 0,
@@ -100,6 +100,14 @@ typedef struct fem_coeffs {
                                 input or output */
     void *workspace;         /* mixed degree only: fem_workspace_bytes(nel) bytes, 256-B aligned */
     size_t workspace_bytes;
+    const double *jac;       /* NULL, or supplied Jacobian terms (the NOJAC variant of section 4):
+                                10 doubles per element and Gauss point, detJ then J^{-1} row-major
+                                (J[a][b] = dx_a/dxi_b), point q = q1 + n q2 + n^2 q3; element e's
+                                Nq = Ns records start at record e Nq (uniform p) or b_off[e]
+                                (mixed degree, which then needs b_off even without out_b). They
+                                replace the computation from geom, which then serves FIELD mode's
+                                x_q only and may be NULL in the other modes. fem_jacobian_terms
+                                writes them; any other source is taken as given. */
 } fem_coeffs;
 
 /* Make `device` current, build the FP64 reference tables for p = 1..7 (quadrature, 1-D
@@ -115,12 +123,23 @@ int fem_finalize(void);
  *   nel    >= 0; nel == 0 returns FEM_OK and enqueues nothing
  *   p      1..7 for a uniform degree; 0 selects the per-element degrees coeffs->degree, which
  *          then also needs coeffs->a_off, coeffs->b_off (if out_b) and coeffs->workspace
- *   geom   [nel][8][3] FP64 vertex coordinates
+ *   geom   [nel][8][3] FP64 vertex coordinates; may be NULL when coeffs->jac is given and the
+ *          mode is not FEM_COEF_FIELD
  *   out_A  uniform p: [nel][Ns][Ns] row-major, unpadded; mixed: element e at a_off[e]
  *   out_b  uniform p: [nel][Ns]; mixed: element e at b_off[e]; may be NULL
  * Outputs are double for FEM_FP64 and float otherwise. */
 int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coeffs, void *out_A,
                   void *out_b, void *stream);
+
+/* Jacobian terms for the NOJAC variant (section 4: the determinant and the 9 entries of the
+ * inverse Jacobian of every element at every quadrature point, read by the integration instead
+ * of recomputed): writes jac in the layout of fem_coeffs.jac, in FP64, from the trilinear map
+ * of geom [nel][8][3]. p = 1..7 for a uniform degree (jac: [nel][Ns][10]); p = 0 takes
+ * degree [nel] and the b_off scan of fem_mixed_offsets (jac: [b_off[nel]][10]; points of an
+ * element whose degree is outside 1..7 are not written). Values equal those the integration
+ * computes itself from the same vertices. Asynchronous on `stream`; allocates nothing. */
+int fem_jacobian_terms(int64_t nel, int p, const double *geom, const int8_t *degree,
+                       const int64_t *b_off, double *jac, void *stream);
 
 /* Bytes of device workspace that a mixed-degree fem_integrate over nel elements needs. */
 size_t fem_workspace_bytes(int64_t nel);

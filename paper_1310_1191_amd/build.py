@@ -22,6 +22,7 @@ HIP_SOURCES = [
     "fem_api.cpp",
     "fem_mixed.hip",
     "fem_timestep.hip",
+    "fem_jacobian.hip",
     "fem_k_f64.hip",
     "fem_k_f32.hip",
     "fem_k_bf16.hip",

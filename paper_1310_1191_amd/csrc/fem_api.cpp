@@ -16,6 +16,7 @@
 #include "fem_launch.h"
 #include "fem_layout.h"
 #include "fem_tables.h"
+#include "fem_jacobian.h"
 #include "fem_mixed.h"
 
 namespace fem {
@@ -313,6 +314,7 @@ KArgs base_args(const fem_coeffs *c, const double *geom, void *out_A, void *out_
     a.geom = geom;
     a.elem = c->elem;
     a.field = c->mode == FEM_COEF_FIELD ? c->field : nullptr;
+    a.jac = c->jac;
     a.out_A = out_A;
     a.out_b = out_b;
     a.status = c->status;
@@ -412,6 +414,28 @@ int fem_finalize(void)
     return FEM_OK;
 }
 
+int fem_jacobian_terms(int64_t nel, int p, const double *geom, const int8_t *degree,
+                       const int64_t *b_off, double *jac, void *stream)
+{
+    if (!g_state.blob) return FEM_ENOTINIT;
+    if (nel < 0) return FEM_EINVAL;
+    if (p < 0 || p > 7) return FEM_EDEGREE;
+    if (p == 0 && !degree) return FEM_EDEGREE;
+    if (p == 0 && !b_off) return FEM_EINVAL;
+    if (nel == 0) return FEM_OK;
+    if (!geom || !jac) return FEM_EINVAL;
+    JacArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nel = nel;
+    a.p = p;
+    a.geom = geom;
+    a.degree = degree;
+    a.b_off = b_off;
+    for (int pp = 1; pp <= 7; ++pp) a.xq[pp] = g_state.deg[pp].xq;
+    a.out = jac;
+    return jacobian_terms_launch(a, (hipStream_t)stream, g_cus) == hipSuccess ? FEM_OK : FEM_EHIP;
+}
+
 size_t fem_workspace_bytes(int64_t nel)
 {
     return nel < 0 ? 0 : mixed_workspace_bytes(nel);
@@ -441,8 +465,8 @@ int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coef
     if (coeffs->mode == FEM_COEF_ELASTIC && p == 0) return FEM_EINVAL;
     if (p == 0 && !coeffs->degree) return FEM_EDEGREE;
     if (nel == 0) return FEM_OK;
-    if (!geom || !out_A || !coeffs->elem) return FEM_EINVAL;
-    if (coeffs->mode == FEM_COEF_FIELD && !coeffs->field) return FEM_EINVAL;
+    if (!out_A || !coeffs->elem || (!geom && !coeffs->jac)) return FEM_EINVAL;
+    if (coeffs->mode == FEM_COEF_FIELD && (!coeffs->field || !geom)) return FEM_EINVAL;
     const hipStream_t s = (hipStream_t)stream;
     KArgs a = base_args(coeffs, geom, out_A, out_b);
     if (p > 0 && coeffs->mode == FEM_COEF_ELASTIC) {
@@ -472,7 +496,7 @@ int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coef
         return dispatch(coeffs->precision, p, a, s, g_cus) == hipSuccess ? FEM_OK : FEM_EHIP;
     }
     // mixed degree: bucket on the device, then one launch per degree over its bucket
-    if (!coeffs->a_off || (out_b && !coeffs->b_off)) return FEM_EINVAL;
+    if (!coeffs->a_off || ((out_b || coeffs->jac) && !coeffs->b_off)) return FEM_EINVAL;
     if (!coeffs->workspace || coeffs->workspace_bytes < mixed_workspace_bytes(nel)) return FEM_EWORKSPACE;
     MixedPlan plan;
     if (mixed_bucket(nel, coeffs->degree, coeffs->workspace, s, &plan) != hipSuccess) return FEM_EHIP;

@@ -34,6 +34,7 @@
 
 #include <type_traits>
 
+#include "fem_geometry.h"
 #include "fem_layout.h"
 
 namespace fem {
@@ -55,6 +56,8 @@ struct KArgs {
     const double *geom;      // [*][8][3]
     const double *elem;      // [*][14] (ELEMENT) or [*][10] (FIELD)
     const double *field;     // [175] (FIELD)
+    const double *jac;       // supplied Jacobian terms [*][Nq][10] = detJ, J^{-1} row-major (element e
+                             // at 10 (b_off ? b_off[e] : e Nq)), or null to compute them from geom
     const int32_t *elist;    // element ids of this launch, or null for 0..nel-1
     const int64_t *seg;      // device {start, count}: use elist + start and nel = count, or null
     const int64_t *a_off;    // [*] element offsets into out_A, or null for e * Ns^2
@@ -551,8 +554,9 @@ __device__ inline Item decode_item(int64_t wi, int64_t nel)
 }
 
 // Fetch the element data of an item into registers (24 coordinates then the coefficient record
-// of each element; entries past the record length or the element count are 0).
-template <class S>
+// of each element; entries past the record length or the element count are 0). With supplied
+// Jacobian terms (SUP) the vertices may be absent and then read as 0.
+template <class S, bool SUP>
 __device__ inline void fetch_elements(const KArgs &a, const int32_t *elist, const Item &it,
                                       int reclen, double (&pf)[S::PFN])
 {
@@ -563,14 +567,17 @@ __device__ inline void fetch_elements(const KArgs &a, const int32_t *elist, cons
         double v = 0.0;
         if (el < it.neg) {
             const int64_t e = element_id(elist, it.e0 + el);
-            if (comp < 24) v = a.geom[e * 24 + comp];
+            if (comp < 24) {
+                if constexpr (SUP) v = a.geom ? a.geom[e * 24 + comp] : 0.0;
+                else v = a.geom[e * 24 + comp];
+            }
             else if (comp - 24 < reclen) v = a.elem[e * reclen + (comp - 24)];
         }
         pf[k] = v;
     }
 }
 
-template <int P, int PREC, class C>
+template <int P, int PREC, class C, bool SUP>
 __device__ inline void integrate_item(const KArgs &a, const Item &it, const int32_t *elist,
                                       int reclen, unsigned char *smem, const double (&pf)[Shape<P, PREC, C>::PFN],
                                       double (&pf_next)[Shape<P, PREC, C>::PFN], bool has_next,
@@ -624,14 +631,7 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
     // ---- trilinear form x(xi) = sum_S c_S prod_{d in S} xi_d, c_S = 1/8 sum_v X_v prod s_vd ----
     for (int t = tid; t < EG * 24; t += NT) {
         const int el = t / 24, coord = (t % 24) / 8, sub = t % 8;
-        double acc = 0.0;
-#pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            const int neg_bits = __popc(sub & ~v);
-            const double x = s_geo[el * 24 + v * 3 + coord];
-            acc += (neg_bits & 1) ? -x : x;
-        }
-        s_tc[t] = 0.125 * acc;
+        s_tc[t] = trilinear_coeff(s_geo + el * 24, coord, sub);
     }
     __syncthreads();
 
@@ -643,14 +643,8 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
             if (el >= neg || q >= NQ) continue;
             const int q1 = q % N, q2 = (q / N) % N, q3 = q / (N * N);
             const double x1 = s_qw[q1], x2 = s_qw[q2], x3 = s_qw[q3];
-            const double *tc = s_tc + el * 24;
             double xq[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double *k = tc + c * 8;
-                xq[c] = k[0] + k[1] * x1 + k[2] * x2 + k[4] * x3 + x1 * (k[3] * x2 + k[5] * x3) +
-                        x2 * x3 * (k[6] + k[7] * x1);
-            }
+            trilinear_point(s_tc + el * 24, x1, x2, x3, xq);
             double g[7];
             eval_fields(s_fld, xq, g);
             double *stage = reinterpret_cast<double *>(s_D + (size_t)t * S::DSTR);
@@ -674,32 +668,19 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
         const int q1 = q % N, q2 = (q / N) % N, q3 = q / (N * N);
         const double x1 = s_qw[q1], x2 = s_qw[q2], x3 = s_qw[q3];
         const double w = s_qw[N + q1] * s_qw[N + q2] * s_qw[N + q3];
-        const double *tc = s_tc + el * 24;
-        double J[3][3];
+        double Ji[3][3], det;
+        if constexpr (SUP) {
+            // supplied terms (the NOJAC variant of section 4): detJ, then J^{-1} row-major
+            const int64_t e = element_id(elist, e0 + el);
+            const double *jt = a.jac + ((a.b_off ? a.b_off[e] : e * NQ) + q) * 10;
+            det = jt[0];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double *k = tc + c * 8;
-            J[c][0] = k[1] + k[3] * x2 + k[5] * x3 + k[7] * x2 * x3;
-            J[c][1] = k[2] + k[3] * x1 + k[6] * x3 + k[7] * x1 * x3;
-            J[c][2] = k[4] + k[5] * x1 + k[6] * x2 + k[7] * x1 * x2;
+            for (int m = 0; m < 3; ++m)
+#pragma unroll
+                for (int n = 0; n < 3; ++n) Ji[m][n] = jt[1 + 3 * m + n];
+        } else {
+            det = jacobian_terms(s_tc + el * 24, x1, x2, x3, Ji);
         }
-        // J^{-1} = adj(J) / detJ
-        double Ji[3][3];
-        Ji[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-        Ji[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-        Ji[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-        const double det = J[0][0] * Ji[0][0] + J[0][1] * Ji[1][0] + J[0][2] * Ji[2][0];
-        Ji[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-        Ji[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-        Ji[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-        Ji[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-        Ji[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-        Ji[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-        const double id = 1.0 / det;
-#pragma unroll
-        for (int m = 0; m < 3; ++m)
-#pragma unroll
-            for (int n = 0; n < 3; ++n) Ji[m][n] *= id;
 
         const double *rec = s_rec + el * 14;
         double K[3][3], bv[3], cc, ff;
@@ -803,7 +784,7 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
     }
 
     // the element data of the next item travels while this one is multiplied
-    if (has_next) fetch_elements<S>(a, elist, it_next, reclen, pf_next);
+    if (has_next) fetch_elements<S, SUP>(a, elist, it_next, reclen, pf_next);
 
     // ---- producer setup: this thread's column of the tile ----
     using DT2 = typename std::conditional<PREC == PREC_F64, f64x2, f32x2>::type;
@@ -1376,7 +1357,7 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
 // the host (nel) or, for the buckets of a mixed-degree call, from device memory (seg), so no
 // host synchronisation is needed between bucketing and integration. Returns at once if wi is
 // past the last item. Every thread of the workgroup must call it with the same arguments.
-template <int P, int PREC, class C>
+template <int P, int PREC, class C, bool SUP>
 __device__ inline void run_items(const KArgs &a, int64_t wi, const int64_t stride, unsigned char *smem)
 {
     using S = Shape<P, PREC, C>;
@@ -1440,13 +1421,13 @@ __device__ inline void run_items(const KArgs &a, int64_t wi, const int64_t strid
 
     Item it = decode_item<S>(wi, nel);
     double pf[S::PFN], pf_next[S::PFN];
-    fetch_elements<S>(a, elist, it, reclen, pf);
+    fetch_elements<S, SUP>(a, elist, it, reclen, pf);
     __syncthreads();
     for (;;) {
         const int64_t wn = wi + stride;
         const bool has_next = wn < total;
         const Item itn = has_next ? decode_item<S>(wn, nel) : it;
-        integrate_item<P, PREC, C>(a, it, elist, reclen, smem, pf, pf_next, has_next, itn);
+        integrate_item<P, PREC, C, SUP>(a, it, elist, reclen, smem, pf, pf_next, has_next, itn);
         if (!has_next) break;
         wi = wn;
         it = itn;
@@ -1455,13 +1436,14 @@ __device__ inline void run_items(const KArgs &a, int64_t wi, const int64_t strid
     }
 }
 
-// One degree per launch: a persistent grid over that degree's work items.
-template <int P, int PREC, class C>
+// One degree per launch: a persistent grid over that degree's work items. SUP: the Jacobian
+// terms are read from a.jac (a separate instance, so the computing one carries none of it).
+template <int P, int PREC, class C, bool SUP>
 __global__ void __launch_bounds__(C::NW * 64) __attribute__((amdgpu_waves_per_eu(C::OCC, 8)))
 k_integrate(const KArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    run_items<P, PREC, C>(a, blockIdx.x, gridDim.x, smem);
+    run_items<P, PREC, C, SUP>(a, blockIdx.x, gridDim.x, smem);
 }
 
 // Every degree in one launch. The work items of the degrees, heaviest degree first, form one
@@ -1471,7 +1453,7 @@ struct MixedKArgs {
     KArgs deg[7];  // deg[p - 1]: the bucket of degree p (seg = its {start, count})
 };
 
-template <int P, int PREC, class C>
+template <int P, int PREC, class C, bool SUP>
 __device__ inline void mixed_segment(const KArgs &a, int64_t &base, unsigned char *smem)
 {
     using S = Shape<P, PREC, C>;
@@ -1483,26 +1465,26 @@ __device__ inline void mixed_segment(const KArgs &a, int64_t &base, unsigned cha
         // first index >= base of the form blockIdx.x + k g, relative to base
         const int64_t wi = (((int64_t)blockIdx.x - base) % g + g) % g;
         if (wi < total) {
-            run_items<P, PREC, C>(a, wi, g, smem);
+            run_items<P, PREC, C, SUP>(a, wi, g, smem);
             __syncthreads();  // the next degree's constants reuse the LDS
         }
     }
     base += total;
 }
 
-template <int PREC, class C1, class C2, class C3, class C4, class C5, class C6, class C7>
+template <int PREC, bool SUP, class C1, class C2, class C3, class C4, class C5, class C6, class C7>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 8)))
 k_integrate_mixed(const MixedKArgs m)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     int64_t base = 0;
-    mixed_segment<7, PREC, C7>(m.deg[6], base, smem);
-    mixed_segment<6, PREC, C6>(m.deg[5], base, smem);
-    mixed_segment<5, PREC, C5>(m.deg[4], base, smem);
-    mixed_segment<4, PREC, C4>(m.deg[3], base, smem);
-    mixed_segment<3, PREC, C3>(m.deg[2], base, smem);
-    mixed_segment<2, PREC, C2>(m.deg[1], base, smem);
-    mixed_segment<1, PREC, C1>(m.deg[0], base, smem);
+    mixed_segment<7, PREC, C7, SUP>(m.deg[6], base, smem);
+    mixed_segment<6, PREC, C6, SUP>(m.deg[5], base, smem);
+    mixed_segment<5, PREC, C5, SUP>(m.deg[4], base, smem);
+    mixed_segment<4, PREC, C4, SUP>(m.deg[3], base, smem);
+    mixed_segment<3, PREC, C3, SUP>(m.deg[2], base, smem);
+    mixed_segment<2, PREC, C2, SUP>(m.deg[1], base, smem);
+    mixed_segment<1, PREC, C1, SUP>(m.deg[0], base, smem);
 }
 
 }  // namespace fem

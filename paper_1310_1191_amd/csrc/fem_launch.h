@@ -64,31 +64,41 @@ template <int P, int PREC, int V>
 struct Inst {
     using C = typename VariantCfg<P, family_of(PREC), V>::type;
     using S = Shape<P, PREC, C>;
-    static inline int resident_per_cu = 1;  // workgroups of this instance one CU holds at once
-    static const void *fn() { return reinterpret_cast<const void *>(&k_integrate<P, PREC, C>); }
-    static hipError_t prepare()
+    // workgroups of the instance (computed or supplied Jacobian terms) one CU holds at once
+    static inline int resident_per_cu[2] = {1, 1};
+    template <bool SUP> static const void *fn() { return reinterpret_cast<const void *>(&k_integrate<P, PREC, C, SUP>); }
+    template <bool SUP> static hipError_t prepare_one()
     {
         hipError_t e = hipSuccess;
         if (S::lds_bytes > 65536)
-            e = hipFuncSetAttribute(fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::lds_bytes);
+            e = hipFuncSetAttribute(fn<SUP>(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::lds_bytes);
         if (e != hipSuccess) return e;
         int blocks = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn(), S::NT, S::lds_bytes);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn<SUP>(), S::NT, S::lds_bytes);
         if (e != hipSuccess) return e;
-        resident_per_cu = blocks > 0 ? blocks : 1;
+        resident_per_cu[SUP] = blocks > 0 ? blocks : 1;
         return hipSuccess;
+    }
+    static hipError_t prepare()
+    {
+        const hipError_t e = prepare_one<false>();
+        return e != hipSuccess ? e : prepare_one<true>();
     }
     // a.nel is the exact element count, or an upper bound when a.seg supplies the count. The
     // grid is persistent: at most the workgroups the device holds at once.
-    static hipError_t launch(const KArgs &a, hipStream_t s, int cus)
+    template <bool SUP> static hipError_t launch_one(const KArgs &a, hipStream_t s, int cus)
     {
         const int64_t groups = (a.nel + S::EG - 1) / S::EG;
         const int64_t total = groups * S::RT * S::CT;
-        const int64_t cap = int64_t(cus) * resident_per_cu;
+        const int64_t cap = int64_t(cus) * resident_per_cu[SUP];
         const int64_t grid = total < cap ? total : cap;
         if (grid <= 0) return hipSuccess;
-        hipLaunchKernelGGL((k_integrate<P, PREC, C>), dim3((unsigned)grid), dim3(S::NT), S::lds_bytes, s, a);
+        hipLaunchKernelGGL((k_integrate<P, PREC, C, SUP>), dim3((unsigned)grid), dim3(S::NT), S::lds_bytes, s, a);
         return hipGetLastError();
+    }
+    static hipError_t launch(const KArgs &a, hipStream_t s, int cus)
+    {
+        return a.jac ? launch_one<true>(a, s, cus) : launch_one<false>(a, s, cus);
     }
 };
 
@@ -210,23 +220,28 @@ struct MixedInst {
     static constexpr size_t lds_bytes =
         max2(max2(max2(SP<1>::lds_bytes, SP<2>::lds_bytes), max2(SP<3>::lds_bytes, SP<4>::lds_bytes)),
              max2(max2(SP<5>::lds_bytes, SP<6>::lds_bytes), SP<7>::lds_bytes));
-    static inline int resident_per_cu = 1;
-    static const void *fn()
+    static inline int resident_per_cu[2] = {1, 1};
+    template <bool SUP> static const void *fn()
     {
         return reinterpret_cast<const void *>(
-            &k_integrate_mixed<PREC, CP<1>, CP<2>, CP<3>, CP<4>, CP<5>, CP<6>, CP<7>>);
+            &k_integrate_mixed<PREC, SUP, CP<1>, CP<2>, CP<3>, CP<4>, CP<5>, CP<6>, CP<7>>);
     }
-    static hipError_t prepare()
+    template <bool SUP> static hipError_t prepare_one()
     {
         hipError_t e = hipSuccess;
         if (lds_bytes > 65536)
-            e = hipFuncSetAttribute(fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+            e = hipFuncSetAttribute(fn<SUP>(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
         int blocks = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn(), 256, lds_bytes);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn<SUP>(), 256, lds_bytes);
         if (e != hipSuccess) return e;
-        resident_per_cu = blocks > 0 ? blocks : 1;
+        resident_per_cu[SUP] = blocks > 0 ? blocks : 1;
         return hipSuccess;
+    }
+    static hipError_t prepare()
+    {
+        const hipError_t e = prepare_one<false>();
+        return e != hipSuccess ? e : prepare_one<true>();
     }
     // The bucket sizes are read on the device; the grid is the number of workgroups the device
     // holds at once, capped by an upper bound on the work items (every element in the bucket
@@ -239,11 +254,16 @@ struct MixedInst {
         per_el = per_el > SP<5>::RT * SP<5>::CT ? per_el : SP<5>::RT * SP<5>::CT;
         per_el = per_el > SP<4>::RT * SP<4>::CT ? per_el : SP<4>::RT * SP<4>::CT;
         const int64_t bound = nel * per_el;
-        const int64_t cap = int64_t(cus) * resident_per_cu;
+        const bool sup = m.deg[0].jac != nullptr;
+        const int64_t cap = int64_t(cus) * resident_per_cu[sup];
         const int64_t grid = bound < cap ? bound : cap;
         if (grid <= 0) return hipSuccess;
-        hipLaunchKernelGGL((k_integrate_mixed<PREC, CP<1>, CP<2>, CP<3>, CP<4>, CP<5>, CP<6>, CP<7>>),
-                           dim3((unsigned)grid), dim3(256), lds_bytes, s, m);
+        if (sup)
+            hipLaunchKernelGGL((k_integrate_mixed<PREC, true, CP<1>, CP<2>, CP<3>, CP<4>, CP<5>, CP<6>, CP<7>>),
+                               dim3((unsigned)grid), dim3(256), lds_bytes, s, m);
+        else
+            hipLaunchKernelGGL((k_integrate_mixed<PREC, false, CP<1>, CP<2>, CP<3>, CP<4>, CP<5>, CP<6>, CP<7>>),
+                               dim3((unsigned)grid), dim3(256), lds_bytes, s, m);
         return hipGetLastError();
     }
 };

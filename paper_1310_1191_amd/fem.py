@@ -39,6 +39,7 @@ class fem_coeffs(ctypes.Structure):
         ("status", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
+        ("jac", ctypes.c_void_p),
     ]
 
 
@@ -68,6 +69,7 @@ def load():
     lib.fem_workspace_bytes.argtypes = [ctypes.c_int64]
     lib.fem_workspace_bytes.restype = ctypes.c_size_t
     lib.fem_mixed_offsets.argtypes = [ctypes.c_int64, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.fem_jacobian_terms.argtypes = [ctypes.c_int64, ctypes.c_int, vp, vp, vp, vp, vp]
     lib.fem_strerror.argtypes = [ctypes.c_int]
     lib.fem_strerror.restype = ctypes.c_char_p
     lib.fem_abi_version.argtypes = []
@@ -89,7 +91,7 @@ def exported_symbols():
     return ["fem_init", "fem_finalize", "fem_integrate", "fem_workspace_bytes",
             "fem_mixed_offsets", "fem_field_advance", "fem_reference_tables", "fem_strerror",
             "fem_abi_version", "fem_variant_count", "fem_get_variant", "fem_set_variant",
-            "fem_autotune", "fem_load_tuning", "fem_mixed_variant"]
+            "fem_autotune", "fem_load_tuning", "fem_mixed_variant", "fem_jacobian_terms"]
 
 
 # ---------------------------------------------------------------------------------------------
@@ -143,6 +145,11 @@ def fem_mixed_offsets(nel: int, degree: int, a_off: int, b_off: int, workspace: 
                       workspace_bytes: int, stream: int | None) -> int:
     return int(load().fem_mixed_offsets(int(nel), degree, a_off, b_off, workspace,
                                          int(workspace_bytes), stream))
+
+
+def fem_jacobian_terms(nel: int, p: int, geom: int, degree: int | None, b_off: int | None,
+                       jac: int, stream: int | None) -> int:
+    return int(load().fem_jacobian_terms(int(nel), int(p), geom, degree, b_off, jac, stream))
 
 
 def fem_field_advance(field: int, deltas: int, nsteps: int, step: int, stream: int | None) -> int:
@@ -231,7 +238,7 @@ def _stream(stream):
 
 
 def make_coeffs(precision, mode, elem, field=None, degree=None, a_off=None, b_off=None,
-                status=None, workspace=None) -> fem_coeffs:
+                status=None, workspace=None, jac=None) -> fem_coeffs:
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     c = fem_coeffs()
     c.precision = prec
@@ -244,6 +251,7 @@ def make_coeffs(precision, mode, elem, field=None, degree=None, a_off=None, b_of
     c.status = status.data_ptr() if status is not None else None
     c.workspace = workspace.data_ptr() if workspace is not None else None
     c.workspace_bytes = workspace.numel() if workspace is not None else 0
+    c.jac = jac.data_ptr() if jac is not None else None
     return c
 
 
@@ -254,23 +262,26 @@ def out_dtype(precision):
 
 
 def integrate(geom, elem, p: int, precision="split_bf16", mode: int = ELEMENT, field=None,
-              out_A=None, out_b=None, status=None, with_b: bool = True, stream=None):
+              out_A=None, out_b=None, status=None, with_b: bool = True, stream=None, jac=None):
     """Uniform degree p: returns (A [nel, Ns, Ns], b [nel, Ns] or None) on the device; for
-    mode ELASTIC (elem [nel, 5] = E, nu, f1, f2, f3) A is [nel, 3, 3, Ns, Ns], b [nel, 3, Ns]."""
+    mode ELASTIC (elem [nel, 5] = E, nu, f1, f2, f3) A is [nel, 3, 3, Ns, Ns], b [nel, 3, Ns].
+    ``jac`` ([nel, Ns, 10], see ``jacobian_terms``) supplies the Jacobian terms; ``geom`` may
+    then be None outside FIELD mode."""
     torch = _torch()
-    fem_init(geom.device.index or 0)
-    nel = geom.shape[0]
+    fem_init(elem.device.index or 0)
+    nel = elem.shape[0]
     ns = (p + 1) ** 3 if 1 <= p <= 7 else 0
     dt = out_dtype(precision)
     _check(geom, torch.float64, "geom")
     _check(elem, torch.float64, "elem")
     _check(field, torch.float64, "field")
+    _check(jac, torch.float64, "jac")
     ashape, bshape = ((nel, 3, 3, ns, ns), (nel, 3, ns)) if mode == ELASTIC else ((nel, ns, ns), (nel, ns))
     if out_A is None:
-        out_A = torch.empty(ashape, dtype=dt, device=geom.device)
+        out_A = torch.empty(ashape, dtype=dt, device=elem.device)
     if out_b is None and with_b:
-        out_b = torch.empty(bshape, dtype=dt, device=geom.device)
-    c = make_coeffs(precision, mode, elem, field=field, status=status)
+        out_b = torch.empty(bshape, dtype=dt, device=elem.device)
+    c = make_coeffs(precision, mode, elem, field=field, status=status, jac=jac)
     rc = fem_integrate(nel, p, _ptr(geom), c, _ptr(out_A), _ptr(out_b), _stream(stream))
     if rc != FEM_OK:
         raise FemError(rc, "fem_integrate")
@@ -296,28 +307,50 @@ def mixed_offsets(degree, workspace=None, stream=None):
 
 def integrate_mixed(geom, elem, degree, precision="split_bf16", mode: int = ELEMENT, field=None,
                     a_off=None, b_off=None, out_A=None, out_b=None, status=None, workspace=None,
-                    with_b: bool = True, stream=None):
-    """Per-element degrees: returns (A packed, b packed, a_off, b_off) on the device."""
+                    with_b: bool = True, stream=None, jac=None):
+    """Per-element degrees: returns (A packed, b packed, a_off, b_off) on the device. ``jac``
+    (packed by b_off, see ``jacobian_terms``) supplies the Jacobian terms."""
     torch = _torch()
-    fem_init(geom.device.index or 0)
-    nel = geom.shape[0]
+    dev = elem.device
+    fem_init(dev.index or 0)
+    nel = elem.shape[0]
     if workspace is None:
-        workspace = torch.empty(fem_workspace_bytes(nel), dtype=torch.uint8, device=geom.device)
+        workspace = torch.empty(fem_workspace_bytes(nel), dtype=torch.uint8, device=dev)
     if a_off is None or b_off is None:
         a_off, b_off = mixed_offsets(degree, workspace=workspace, stream=stream)
     dt = out_dtype(precision)
     # output sizes are read back only when the outputs are allocated here; with caller-provided
     # outputs the call enqueues work and never synchronises (stream capture is possible)
     if out_A is None:
-        out_A = torch.empty(int(a_off[-1].item()), dtype=dt, device=geom.device)
+        out_A = torch.empty(int(a_off[-1].item()), dtype=dt, device=dev)
     if out_b is None and with_b:
-        out_b = torch.empty(int(b_off[-1].item()), dtype=dt, device=geom.device)
+        out_b = torch.empty(int(b_off[-1].item()), dtype=dt, device=dev)
     c = make_coeffs(precision, mode, elem, field=field, degree=degree, a_off=a_off, b_off=b_off,
-                    status=status, workspace=workspace)
+                    status=status, workspace=workspace, jac=jac)
     rc = fem_integrate(nel, 0, _ptr(geom), c, _ptr(out_A), _ptr(out_b), _stream(stream))
     if rc != FEM_OK:
         raise FemError(rc, "fem_integrate")
     return out_A, out_b, a_off, b_off
+
+
+def jacobian_terms(geom, p: int = 0, degree=None, b_off=None, out=None, stream=None):
+    """Device Jacobian terms of the NOJAC variant: [nel, Ns, 10] for a uniform p, or packed by
+    the b_off scan ([b_off[-1], 10]) for per-element degrees (p = 0 with degree, b_off)."""
+    torch = _torch()
+    fem_init(geom.device.index or 0)
+    nel = geom.shape[0]
+    _check(geom, torch.float64, "geom")
+    if out is None:
+        if p > 0:
+            ns = (p + 1) ** 3 if p <= 7 else 0
+            out = torch.empty((nel, ns, 10), dtype=torch.float64, device=geom.device)
+        else:
+            out = torch.empty((int(b_off[-1].item()), 10), dtype=torch.float64, device=geom.device)
+    rc = fem_jacobian_terms(nel, p, _ptr(geom), _ptr(degree), _ptr(b_off), _ptr(out),
+                            _stream(stream))
+    if rc != FEM_OK:
+        raise FemError(rc, "fem_jacobian_terms")
+    return out
 
 
 def field_advance(field, deltas, step, stream=None):

@@ -38,7 +38,7 @@ def test_binding_wraps_every_symbol():
 
 def test_host_only_calls(lib):
     from paper_1310_1191_amd import fem
-    assert fem.fem_abi_version() == 1
+    assert fem.fem_abi_version() == 2
     assert fem.fem_strerror(0) == "success"
     assert "init" in fem.fem_strerror(fem.FEM_ENOTINIT)
     assert fem.fem_strerror(-99) == "unknown status"
@@ -55,12 +55,23 @@ def test_calls_before_init_are_rejected_on_the_host(lib):
     assert lib.fem_finalize() == fem.FEM_ENOTINIT
 
 
-def test_c_struct_layout_matches_header():
+def test_c_struct_layout_matches_header(tmp_path):
+    """The binding's fem_coeffs against the C compiler's layout of the header's struct."""
+    import subprocess
     from paper_1310_1191_amd import fem
-    # int32, int32, 7 pointers, size_t on LP64
-    assert ctypes.sizeof(fem.fem_coeffs) == 8 + 7 * 8 + 8
-    assert fem.fem_coeffs.elem.offset == 8
-    assert fem.fem_coeffs.workspace_bytes.offset == 8 + 7 * 8
+    names = [f[0] for f in fem.fem_coeffs._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"fem.h\"\nint main(void){\n"
+                   '  printf("%zu\\n", sizeof(fem_coeffs));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof(fem_coeffs, {n}));\n' for n in names)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c11", f"-I{inc}", str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(fem.fem_coeffs)
+    assert got[1:] == [getattr(fem.fem_coeffs, n).offset for n in names]
 
 
 @pytest.mark.parametrize("p", range(1, 8))

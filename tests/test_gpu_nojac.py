@@ -1,0 +1,196 @@
+"""GPU parity of the NOJAC variant (section 4: per-point detJ and J^{-1} supplied instead of
+computed): the device Jacobian terms against the oracle's, and integration with supplied terms
+against the FP64 oracle for every degree and path, uniform and mixed degree, scalar and
+elasticity problems, with the vertices left out where the mode allows it."""
+import numpy as np
+import pytest
+
+from gpu_cases import TOL_A, TOL_B, cdr_case, log, oracle_uniform, rel_fro, rel_vec, to_dev
+from paper_1310_1191_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fem():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    from paper_1310_1191_amd import fem as F
+    F.fem_init(0)
+    return F
+
+
+def terms_error(jt, ref):
+    """Max over points of |detJ - detJ*| / |detJ*| and of max|Ji - Ji*| / max|Ji*|."""
+    ed = np.abs(jt[..., 0] - ref[..., 0]) / np.abs(ref[..., 0])
+    ei = np.abs(jt[..., 1:] - ref[..., 1:]).max(axis=-1) / np.abs(ref[..., 1:]).max(axis=-1)
+    return ed.max(), ei.max()
+
+
+@pytest.mark.parametrize("p", range(1, 8))
+def test_jacobian_terms_match_oracle(fem, p):
+    import oracle
+    import torch
+    geom, _ = cdr_case(p)
+    (g,) = to_dev(geom)
+    jt = fem.jacobian_terms(g, p)
+    torch.cuda.synchronize()
+    ed, ei = terms_error(jt.cpu().numpy(), oracle.jacobian_terms(geom, p))
+    log(f"[nojac] terms p={p} nel={geom.shape[0]} detJ {ed:.2e} Jinv {ei:.2e}")
+    assert ed <= 1e-13 and ei <= 1e-13
+
+
+def test_jacobian_terms_mixed_match_oracle(fem):
+    import oracle
+    import torch
+    w = synth.make(4, grid=(7, 5, 4))
+    g, d = to_dev(w.geom, w.degree)
+    a_off, b_off = fem.mixed_offsets(d)
+    jt = fem.jacobian_terms(g, 0, degree=d, b_off=b_off)
+    torch.cuda.synchronize()
+    ed, ei = terms_error(jt.cpu().numpy(), oracle.jacobian_terms(w.geom, degree=w.degree))
+    assert ed <= 1e-13 and ei <= 1e-13
+
+
+@pytest.mark.parametrize("p", range(1, 8))
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "split_fp16"])
+def test_supplied_terms_parity(fem, p, prec):
+    """Terms from the oracle, no vertices passed (ELEMENT mode), against the oracle's vertex path."""
+    import oracle
+    import torch
+    geom, coef, A_ref, b_ref, _ = oracle_uniform(p)
+    jac = oracle.jacobian_terms(geom, p)
+    c, j = to_dev(coef, jac)
+    status = torch.zeros(2, dtype=torch.int32, device="cuda")
+    A, b = fem.integrate(None, c, p, precision=prec, jac=j, status=status)
+    torch.cuda.synchronize()
+    ea = rel_fro(A.double().cpu().numpy(), A_ref)
+    eb = rel_vec(b.double().cpu().numpy(), b_ref)
+    log(f"[nojac] p={p} prec={prec} nel={geom.shape[0]} errA max={ea.max():.3e} errb max={eb.max():.3e}")
+    assert status.cpu().tolist() == [0, 0]
+    assert ea.max() <= TOL_A[prec] and eb.max() <= TOL_B[prec]
+
+
+@pytest.mark.parametrize("p", [2, 4, 6])
+def test_device_terms_reproduce_the_vertex_path(fem, p):
+    """Terms written by fem_jacobian_terms carry the values the prologue computes itself."""
+    import torch
+    geom, coef = cdr_case(p)
+    g, c = to_dev(geom, coef)
+    jt = fem.jacobian_terms(g, p)
+    for prec in ["fp64", "split_fp16"]:
+        A0, b0 = fem.integrate(g, c, p, precision=prec)
+        A1, b1 = fem.integrate(None, c, p, precision=prec, jac=jt)
+        torch.cuda.synchronize()
+        d = rel_fro(A1.double().cpu().numpy(), A0.double().cpu().numpy()).max()
+        db = rel_vec(b1.double().cpu().numpy(), b0.double().cpu().numpy()).max()
+        log(f"[nojac] device terms p={p} prec={prec} vs vertex path: A {d:.2e} b {db:.2e}")
+        assert d <= 1e-14 and db <= 1e-14
+
+
+@pytest.mark.parametrize("p", [2, 5])
+def test_supplied_terms_field_mode(fem, p):
+    import oracle
+    import torch
+    w = synth.make(4, grid=(4, 3, 2))
+    A_ref, b_ref, _ = oracle.integrate(w.geom, w.coef, p=p, mode=oracle.FIELD, field=w.field)
+    g, c, f, j = to_dev(w.geom, w.coef, w.field, oracle.jacobian_terms(w.geom, p))
+    for prec in ["fp64", "fp32", "split_fp16"]:
+        A, b = fem.integrate(g, c, p, precision=prec, mode=fem.FIELD, field=f, jac=j)
+        torch.cuda.synchronize()
+        ea = rel_fro(A.double().cpu().numpy(), A_ref)
+        eb = rel_vec(b.double().cpu().numpy(), b_ref)
+        log(f"[nojac] FIELD p={p} prec={prec} errA max={ea.max():.3e}")
+        assert ea.max() <= TOL_A[prec] and eb.max() <= TOL_B[prec]
+
+
+@pytest.mark.parametrize("p", [2, 4, 7])
+def test_supplied_terms_elasticity(fem, p):
+    import oracle
+    import torch
+    rng = np.random.default_rng(70 + p)
+    grid = {2: (3, 2, 2), 4: (2, 1, 1), 7: (1, 1, 1)}[p]
+    geom = synth.element_vertices(synth.node_grid(*grid, 0.15, rng))
+    coef = synth.elastic_coeffs(geom.shape[0], rng)
+    A_ref, b_ref, _ = oracle.integrate_elastic(geom, coef, p)
+    c, j = to_dev(coef, oracle.jacobian_terms(geom, p))
+    nel, ns = geom.shape[0], (p + 1) ** 3
+    for prec in ["fp64", "split_fp16"]:
+        A, b = fem.integrate(None, c, p, precision=prec, mode=fem.ELASTIC, jac=j)
+        torch.cuda.synchronize()
+        full = lambda X: X.transpose(0, 1, 3, 2, 4).reshape(nel, 3 * ns, 3 * ns)
+        ea = rel_fro(full(A.double().cpu().numpy()), full(A_ref))
+        eb = rel_vec(b.double().cpu().numpy().reshape(nel, -1), b_ref.reshape(nel, -1))
+        log(f"[nojac] elastic p={p} prec={prec} errA max={ea.max():.3e}")
+        assert ea.max() <= TOL_A[prec] and eb.max() <= TOL_B[prec]
+
+
+@pytest.mark.parametrize("strategy", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "split_fp16"])
+def test_supplied_terms_mixed_degree(fem, prec, strategy):
+    import oracle
+    import torch
+    w = synth.make(4, grid=(7, 5, 4))
+    A_ref, b_ref, _, a_ref, b_ref_off = oracle.integrate(w.geom, w.coef, degree=w.degree,
+                                                         mode=oracle.FIELD, field=w.field)
+    g, c, f, d = to_dev(w.geom, w.coef, w.field, w.degree)
+    a_off, b_off = fem.mixed_offsets(d)
+    jt = fem.jacobian_terms(g, 0, degree=d, b_off=b_off)
+    code = fem.PRECISIONS[prec]
+    saved = fem.fem_get_variant(0, code)
+    fem.fem_set_variant(0, code, strategy)
+    try:
+        A, b, _, _ = fem.integrate_mixed(g, c, d, precision=prec, mode=fem.FIELD, field=f,
+                                         a_off=a_off, b_off=b_off, jac=jt)
+        torch.cuda.synchronize()
+    finally:
+        fem.fem_set_variant(0, code, saved)
+    A = A.double().cpu().numpy()
+    b = b.double().cpu().numpy()
+    ea = max(rel_fro(A[a_ref[e]:a_ref[e + 1]].reshape(1, -1, 1),
+                     A_ref[a_ref[e]:a_ref[e + 1]].reshape(1, -1, 1))[0] for e in range(w.nel))
+    eb = max(rel_vec(b[None, b_ref_off[e]:b_ref_off[e + 1]],
+                     b_ref[None, b_ref_off[e]:b_ref_off[e + 1]])[0] for e in range(w.nel))
+    log(f"[nojac] mixed prec={prec} strategy={strategy} errA max={ea:.3e} errb max={eb:.3e}")
+    assert ea <= TOL_A[prec] and eb <= TOL_B[prec]
+
+
+def test_supplied_terms_status(fem):
+    import oracle
+    import torch
+    geom, coef = cdr_case(2)
+    jac = oracle.jacobian_terms(geom, 2)
+    jac[3, 7, 0] = -jac[3, 7, 0]       # one point of element 3 with detJ < 0
+    jac[5, 0, 2] = np.inf              # a non-finite inverse entry in element 5
+    c, j = to_dev(coef, jac)
+    status = torch.zeros(2, dtype=torch.int32, device="cuda")
+    fem.integrate(None, c, 2, precision="fp64", jac=j, status=status)
+    torch.cuda.synchronize()
+    assert status.cpu().tolist() == [1, 1]
+
+
+def test_supplied_terms_argument_errors(fem):
+    import torch
+    geom, coef = cdr_case(2)
+    g, c = to_dev(geom, coef)
+    nel = geom.shape[0]
+    jt = fem.jacobian_terms(g, 2)
+    out = torch.empty(nel * 27 * 27, device="cuda")
+    # FIELD mode needs the vertices for x_q even with supplied terms
+    fld = torch.zeros(175, dtype=torch.float64, device="cuda")
+    cc = fem.make_coeffs("fp32", fem.FIELD, c, field=fld, jac=jt)
+    assert fem.fem_integrate(nel, 2, None, cc, out.data_ptr(), None, None) == fem.FEM_EINVAL
+    # neither vertices nor terms
+    cc = fem.make_coeffs("fp32", fem.ELEMENT, c)
+    assert fem.fem_integrate(nel, 2, None, cc, out.data_ptr(), None, None) == fem.FEM_EINVAL
+    # mixed degree with terms needs b_off even without out_b
+    d = torch.full((nel,), 2, dtype=torch.int8, device="cuda")
+    a_off, _ = fem.mixed_offsets(d)
+    ws = torch.empty(fem.fem_workspace_bytes(nel), dtype=torch.uint8, device="cuda")
+    cc = fem.make_coeffs("fp32", fem.ELEMENT, c, degree=d, a_off=a_off, workspace=ws, jac=jt)
+    assert fem.fem_integrate(nel, 0, g.data_ptr(), cc, out.data_ptr(), None, None) == fem.FEM_EINVAL
+    # the terms writer
+    assert fem.fem_jacobian_terms(nel, 8, g.data_ptr(), None, None, jt.data_ptr(), None) == fem.FEM_EDEGREE
+    assert fem.fem_jacobian_terms(nel, 0, g.data_ptr(), None, None, jt.data_ptr(), None) == fem.FEM_EDEGREE
+    assert fem.fem_jacobian_terms(nel, 2, None, None, None, jt.data_ptr(), None) == fem.FEM_EINVAL
+    assert fem.fem_jacobian_terms(0, 2, None, None, None, None, None) == fem.FEM_OK
