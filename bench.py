@@ -122,12 +122,16 @@ def main():
     ap.add_argument("--compare", default="fp32", help="second path timed for comparison ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="plain",
-                    choices=["plain", "high", "mixed", "timestep", "poisson", "elasticity"],
+                    choices=["plain", "high", "mixed", "timestep", "poisson", "elasticity", "nojac"],
                     help="plain: p = 2, 3, 4 at scale (the headline); high: p = 5, 6, 7 in every "
                          "precision; mixed: 200000 elements of degrees 1..7 with coefficient fields, "
                          "one launch against per-degree launches; timestep: 50 graph-replayed steps "
                          "of 100000 mixed-degree elements; poisson: p = 1; elasticity: the vector "
-                         "model problem (linear elastostatics) for p = 2..7")
+                         "model problem (linear elastostatics) for p = 2..7; nojac: supplied "
+                         "per-point Jacobian terms against computed ones for p = 1..7")
+    ap.add_argument("--nojac", action="store_true",
+                    help="timestep workload: read per-point Jacobian terms written once before the "
+                         "time loop instead of computing them in every step")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain elementwise copy y = -x of MIB MiB three times (the "
                          "known-size kernel that calibrates HBM byte counters)")
@@ -147,7 +151,8 @@ def main():
 
     if args.workload != "plain":
         line = {"high": bench_high, "mixed": bench_mixed, "timestep": bench_timestep,
-                "poisson": bench_poisson, "elasticity": bench_elasticity}[args.workload](
+                "poisson": bench_poisson, "elasticity": bench_elasticity,
+                "nojac": bench_nojac}[args.workload](
             args, torch, fem, synth, dev)
         print(json.dumps(line), flush=True)
         return
@@ -462,11 +467,13 @@ def bench_timestep(args, torch, fem, synth, dev):
         f = f0.clone()
         dl = torch.from_numpy(deltas).to(dev)
         step = torch.zeros(1, dtype=torch.int32, device=dev)
+        # the geometry is fixed over the steps: with --nojac its Jacobian terms are written once
+        jt = fem.jacobian_terms(g, 0, degree=d, b_off=b_off) if args.nojac else None
 
         def one_step(stream=None):
             fem.field_advance(f, dl, step, stream=stream)
             fem.integrate_mixed(g, c, d, precision=prec, mode=fem.FIELD, field=f, a_off=a_off,
-                                b_off=b_off, out_A=A, out_b=b, workspace=ws, stream=stream)
+                                b_off=b_off, out_A=A, out_b=b, workspace=ws, stream=stream, jac=jt)
 
         one_step()  # warm-up outside the capture
         torch.cuda.synchronize()
@@ -516,6 +523,7 @@ def bench_timestep(args, torch, fem, synth, dev):
                                    f"{w.redraws} redraws), phase-shifted coefficient fields, "
                                    "hipGraph replay per step",
                        "gflop_per_step": flops / 1e9,
+                       "jacobian_terms": "supplied (written once)" if args.nojac else "computed",
                        "sample": f"1% of the elements at steps {check} against the FP64 oracle"},
             "results": res, "speedup_split_vs_fp32": res["fp32"]["ms_per_step"] / res["split_fp16"]["ms_per_step"]}
 
@@ -595,6 +603,57 @@ def bench_elasticity(args, torch, fem, synth, dev):
             "config": {"workload": "linear elastostatics hex p=2..7 (3 components, E ~ U[1,10], "
                                    "nu ~ U[0.2,0.4] per element) on the plain and high-order grids",
                        "sample": "4 (p<=5) or 2 random elements per degree against the FP64 oracle"},
+            "per_degree": out}
+
+
+def bench_nojac(args, torch, fem, synth, dev):
+    """Supplied per-point Jacobian terms (detJ and J^{-1}, 80 B per point) against the in-kernel
+    FP64 computation from the 8 vertices (192 B per element), p = 1..7 on the plain-method and
+    high-order grids (p = 1: 128x128x64); the terms writer's own time; sampled errors of the
+    supplied-terms path against the FP64 oracle."""
+    import oracle
+    grids = {1: (128, 128, 64), 2: (64, 64, 64), 3: (64, 64, 32), 4: (64, 32, 32),
+             5: (32, 32, 16), 6: (32, 16, 16), 7: (16, 16, 16)}
+    out = {}
+    for p, grid in grids.items():
+        w = synth.make(2 if p <= 4 else 3, p=p, grid=grid) if p > 1 else synth.make(2, p=2, grid=grid)
+        geom, coef, nel = w.geom, w.coef, w.nel
+        ns = (p + 1) ** 3
+        g, c = torch.from_numpy(geom).to(dev), torch.from_numpy(coef).to(dev)
+        jt = torch.empty((nel, ns, 10), dtype=torch.float64, device=dev)
+        ms_terms = time_calls(torch, lambda: fem.jacobian_terms(g, p, out=jt), max(3, args.steps // 4), 1)
+        idx = np.random.default_rng(p).choice(nel, 4, replace=False)
+        Aref, _, _ = oracle.integrate(geom[idx], coef[idx], p=p, threads=oracle_threads(), with_b=False)
+        res = {"nel": nel, "terms_ms": round(ms_terms, 4),
+               "terms_gbs": round((192 + 80 * ns) * nel / (ms_terms * 1e-3) / 1e9, 1),
+               "extra_bytes_per_element": 80 * ns - 192}
+        for prec in ["split_fp16", "fp32"]:
+            A = torch.empty((nel, ns, ns), dtype=fem.out_dtype(prec), device=dev)
+            b = torch.empty((nel, ns), dtype=fem.out_dtype(prec), device=dev)
+            reps = max(3, args.steps // 4)
+            ms_jac = time_calls(torch, lambda: fem.integrate(g, c, p, precision=prec, out_A=A, out_b=b), reps, 1)
+            ms_sup = time_calls(torch, lambda: fem.integrate(None, c, p, precision=prec, out_A=A, out_b=b,
+                                                             jac=jt), reps, 1)
+            Ag = A[torch.from_numpy(idx).to(dev)].double().cpu().numpy()
+            errs = [rel_fro(Ag[k], Aref[k]) for k in range(idx.size)]
+            res[prec] = {"ms_computed": round(ms_jac, 4), "ms_supplied": round(ms_sup, 4),
+                         "supplied_over_computed": round(ms_sup / ms_jac, 3),
+                         "max_rel_err_sample_supplied": max(errs)}
+            log(f"[bench] nojac p={p} {prec}: computed {ms_jac:.3f} ms, supplied {ms_sup:.3f} ms "
+                f"(terms writer {ms_terms:.3f} ms), max err {max(errs):.2e}")
+            del A, b
+            torch.cuda.empty_cache()
+        out[str(p)] = res
+        del jt
+        torch.cuda.empty_cache()
+    tot_el = sum(out[k]["nel"] for k in out if k != "1")
+    tot_ms = sum(out[k]["split_fp16"]["ms_supplied"] for k in out if k != "1")
+    return {"metric": "element matrices/s (split-precision MFMA, <= 1e-6 relative error)",
+            "value": tot_el / (tot_ms * 1e-3), "unit": "element matrices/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f16x3->f32", "data": "synthetic",
+            "config": {"workload": "cdr-hex p=2..7 on the plain and high-order grids with supplied "
+                                   "per-point Jacobian terms (value); p=1 on 128x128x64 reported only",
+                       "sample": "4 random elements per degree against the FP64 oracle"},
             "per_degree": out}
 
 
