@@ -141,6 +141,36 @@ int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coef
 int fem_jacobian_terms(int64_t nel, int p, const double *geom, const int8_t *degree,
                        const int64_t *b_off, double *jac, void *stream);
 
+/* Host-resident meshes (the end-to-end view of section 6, where the paper times the transfer
+ * of inputs, the kernel and the transfer of results): integrates nel elements of uniform degree
+ * p whose data live in HOST memory, in chunks of `chunk` elements over `nstreams` streams
+ * (1..FEM_STAGED_MAX_STREAMS). Chunk c goes to stream c mod nstreams as {copy geometry and
+ * records to the device, fem_integrate, copy A and b back}; with more than one stream the
+ * copies of one chunk overlap the kernels of others. Host memory from hipHostMalloc (or
+ * torch's pin_memory) lets the copy engines run asynchronously; pageable memory works but
+ * serialises the copies.
+ *   geom, coeffs->elem, coeffs->field, out_A, out_b  HOST pointers, layouts as for
+ *          fem_integrate (uniform p, any coefficient mode); out_b may be NULL
+ *   coeffs->status  HOST int32[2] or NULL: the counts over all chunks are added to it
+ *   coeffs->degree, a_off, b_off and jac must be NULL (FEM_EINVAL otherwise)
+ *   stats  HOST, may be NULL: wall time of the call and per-stage sums of event times
+ * Blocks until the results are in out_A / out_b. The device staging buffers and streams are
+ * allocated on the first call, grown when a larger chunk needs it, reused by later calls and
+ * released by fem_finalize; concurrent calls are serialised. */
+#define FEM_STAGED_MAX_STREAMS 8
+typedef struct fem_staged_stats {
+    double total_ms;     /* host wall time from the first enqueue to the last completion */
+    double h2d_ms;       /* sums over chunks of the event times of each stage */
+    double kernel_ms;
+    double d2h_ms;
+    int64_t h2d_bytes;   /* bytes moved each way */
+    int64_t d2h_bytes;
+    int64_t chunks;
+} fem_staged_stats;
+int fem_integrate_staged(int64_t nel, int p, const double *geom, const fem_coeffs *coeffs,
+                         void *out_A, void *out_b, int64_t chunk, int nstreams,
+                         fem_staged_stats *stats);
+
 /* Bytes of device workspace that a mixed-degree fem_integrate over nel elements needs. */
 size_t fem_workspace_bytes(int64_t nel);
 

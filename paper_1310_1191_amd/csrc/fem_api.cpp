@@ -42,6 +42,7 @@ int variants_split_bf16(int p);
 int variants_split_f16(int p);
 hipError_t field_advance(double *field, const double *deltas, int32_t nsteps, int32_t *step,
                          hipStream_t s);
+void staged_release();
 }  // namespace fem
 
 namespace {
@@ -409,6 +410,7 @@ int fem_finalize(void)
     std::lock_guard<std::mutex> lock(g_mutex);
     if (!g_state.blob) return FEM_ENOTINIT;
     (void)hipDeviceSynchronize();
+    staged_release();
     (void)hipFree(g_state.blob);
     g_state = State();
     return FEM_OK;

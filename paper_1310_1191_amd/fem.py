@@ -43,6 +43,21 @@ class fem_coeffs(ctypes.Structure):
     ]
 
 
+class fem_staged_stats(ctypes.Structure):
+    _fields_ = [
+        ("total_ms", ctypes.c_double),
+        ("h2d_ms", ctypes.c_double),
+        ("kernel_ms", ctypes.c_double),
+        ("d2h_ms", ctypes.c_double),
+        ("h2d_bytes", ctypes.c_int64),
+        ("d2h_bytes", ctypes.c_int64),
+        ("chunks", ctypes.c_int64),
+    ]
+
+
+STAGED_MAX_STREAMS = 8
+
+
 class FemError(RuntimeError):
     def __init__(self, status: int, where: str):
         super().__init__(f"{where}: {fem_strerror(status)} ({status})")
@@ -70,6 +85,9 @@ def load():
     lib.fem_workspace_bytes.restype = ctypes.c_size_t
     lib.fem_mixed_offsets.argtypes = [ctypes.c_int64, vp, vp, vp, vp, ctypes.c_size_t, vp]
     lib.fem_jacobian_terms.argtypes = [ctypes.c_int64, ctypes.c_int, vp, vp, vp, vp, vp]
+    lib.fem_integrate_staged.argtypes = [ctypes.c_int64, ctypes.c_int, vp, ctypes.POINTER(fem_coeffs),
+                                         vp, vp, ctypes.c_int64, ctypes.c_int,
+                                         ctypes.POINTER(fem_staged_stats)]
     lib.fem_strerror.argtypes = [ctypes.c_int]
     lib.fem_strerror.restype = ctypes.c_char_p
     lib.fem_abi_version.argtypes = []
@@ -91,7 +109,8 @@ def exported_symbols():
     return ["fem_init", "fem_finalize", "fem_integrate", "fem_workspace_bytes",
             "fem_mixed_offsets", "fem_field_advance", "fem_reference_tables", "fem_strerror",
             "fem_abi_version", "fem_variant_count", "fem_get_variant", "fem_set_variant",
-            "fem_autotune", "fem_load_tuning", "fem_mixed_variant", "fem_jacobian_terms"]
+            "fem_autotune", "fem_load_tuning", "fem_mixed_variant", "fem_jacobian_terms",
+            "fem_integrate_staged"]
 
 
 # ---------------------------------------------------------------------------------------------
@@ -150,6 +169,15 @@ def fem_mixed_offsets(nel: int, degree: int, a_off: int, b_off: int, workspace: 
 def fem_jacobian_terms(nel: int, p: int, geom: int, degree: int | None, b_off: int | None,
                        jac: int, stream: int | None) -> int:
     return int(load().fem_jacobian_terms(int(nel), int(p), geom, degree, b_off, jac, stream))
+
+
+def fem_integrate_staged(nel: int, p: int, geom: int, coeffs: fem_coeffs, out_A: int,
+                         out_b: int | None, chunk: int, nstreams: int,
+                         stats: fem_staged_stats | None) -> int:
+    """Raw call: integer HOST addresses, returns the status code."""
+    return int(load().fem_integrate_staged(int(nel), int(p), geom, ctypes.byref(coeffs), out_A,
+                                           out_b, int(chunk), int(nstreams),
+                                           ctypes.byref(stats) if stats is not None else None))
 
 
 def fem_field_advance(field: int, deltas: int, nsteps: int, step: int, stream: int | None) -> int:
@@ -331,6 +359,44 @@ def integrate_mixed(geom, elem, degree, precision="split_bf16", mode: int = ELEM
     if rc != FEM_OK:
         raise FemError(rc, "fem_integrate")
     return out_A, out_b, a_off, b_off
+
+
+def _host(t, dtype, name):
+    if t is None:
+        return
+    if t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} host tensor")
+
+
+def integrate_staged(geom, elem, p: int, precision="split_fp16", mode: int = ELEMENT, field=None,
+                     chunk: int = 16384, nstreams: int = 3, out_A=None, out_b=None,
+                     with_b: bool = True, status=None):
+    """Host-resident mesh (CPU tensors; pinned memory lets the copies overlap the kernels):
+    returns (A, b, stats) with A, b host tensors (pinned when allocated here) and stats the
+    per-stage times of fem_integrate_staged as a dict. ``status``: host int32[2], added to."""
+    torch = _torch()
+    fem_init(torch.cuda.current_device())
+    nel = elem.shape[0]
+    ns = (p + 1) ** 3 if 1 <= p <= 7 else 0
+    dt = out_dtype(precision)
+    _host(geom, torch.float64, "geom")
+    _host(elem, torch.float64, "elem")
+    _host(field, torch.float64, "field")
+    _host(status, torch.int32, "status")
+    ashape, bshape = ((nel, 3, 3, ns, ns), (nel, 3, ns)) if mode == ELASTIC else ((nel, ns, ns), (nel, ns))
+    if out_A is None:
+        out_A = torch.empty(ashape, dtype=dt, pin_memory=True)
+    if out_b is None and with_b:
+        out_b = torch.empty(bshape, dtype=dt, pin_memory=True)
+    _host(out_A, dt, "out_A")
+    _host(out_b, dt, "out_b")
+    c = make_coeffs(precision, mode, elem, field=field, status=status)
+    st = fem_staged_stats()
+    rc = fem_integrate_staged(nel, p, _ptr(geom), c, _ptr(out_A), _ptr(out_b), chunk, nstreams, st)
+    if rc != FEM_OK:
+        raise FemError(rc, "fem_integrate_staged")
+    stats = {k: getattr(st, k) for k, _ in fem_staged_stats._fields_}
+    return out_A, out_b, stats
 
 
 def jacobian_terms(geom, p: int = 0, degree=None, b_off=None, out=None, stream=None):

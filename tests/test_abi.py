@@ -55,23 +55,25 @@ def test_calls_before_init_are_rejected_on_the_host(lib):
     assert lib.fem_finalize() == fem.FEM_ENOTINIT
 
 
-def test_c_struct_layout_matches_header(tmp_path):
-    """The binding's fem_coeffs against the C compiler's layout of the header's struct."""
+@pytest.mark.parametrize("struct", ["fem_coeffs", "fem_staged_stats"])
+def test_c_struct_layout_matches_header(tmp_path, struct):
+    """The binding's structs against the C compiler's layout of the header's structs."""
     import subprocess
     from paper_1310_1191_amd import fem
-    names = [f[0] for f in fem.fem_coeffs._fields_]
+    cls = getattr(fem, struct)
+    names = [f[0] for f in cls._fields_]
     src = tmp_path / "layout.c"
     src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"fem.h\"\nint main(void){\n"
-                   '  printf("%zu\\n", sizeof(fem_coeffs));\n'
-                   + "".join(f'  printf("%zu\\n", offsetof(fem_coeffs, {n}));\n' for n in names)
+                   f'  printf("%zu\\n", sizeof({struct}));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof({struct}, {n}));\n' for n in names)
                    + "  return 0;\n}\n")
     exe = tmp_path / "layout"
     inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
     subprocess.run(["gcc", "-std=c11", f"-I{inc}", str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
                                           text=True).stdout.split()]
-    assert got[0] == ctypes.sizeof(fem.fem_coeffs)
-    assert got[1:] == [getattr(fem.fem_coeffs, n).offset for n in names]
+    assert got[0] == ctypes.sizeof(cls)
+    assert got[1:] == [getattr(cls, n).offset for n in names]
 
 
 @pytest.mark.parametrize("p", range(1, 8))
