@@ -53,7 +53,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ["fem_kernel.h", "fem_launch.h", "fem_layout.h"]
+KERNEL_SOURCES = ["fem_kernel.h", "fem_launch.h", "fem_layout.h", "fem_geometry.h"]
 
 
 def kernel_source_hash() -> str:
