@@ -1079,14 +1079,6 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
                 cfw[j] = col_from(pt, j);
             }
         }
-#ifdef FEM_SCHED_VALU_PER_MFMA
-        // interleave: one MFMA, then a few VALU instructions, repeated
-#pragma unroll
-        for (int k = 0; k < C::WM * C::WN * (S::SPLIT ? 3 : 1); ++k) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x002, FEM_SCHED_VALU_PER_MFMA, 0);
-        }
-#endif
     };
 
     auto consume_chunk = [&](int ch, const unsigned char *cbuf, const unsigned char *rbuf) {
