@@ -140,7 +140,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the integration shards "
-              "elements across GPUs without communication, and this build measures one GPU's "
+              "elements across GPUs without communication, and this benchmark measures one GPU's "
               "share.", file=sys.stderr)
         sys.exit(2)
 
