@@ -6,7 +6,8 @@ default tile variant of each degree and precision, the default mixed-degree stra
   and their gradients to zero, so each row sum of A is c / f times the load-vector entry
   (A 1 = (c / f) b, ELEMENT mode), checked where |f| is not small;
 * the mixed-degree batch of 200000 elements and the 50-step time-stepped replay of 100000
-  elements on their samples.
+  elements on their samples;
+* the limits: an output indexed past 2^31 entries, and meshes scaled by 1e-4 and 1e4.
 """
 import numpy as np
 import pytest
@@ -164,3 +165,51 @@ def test_time_steps_full_size(fem):
             assert ea <= TOL_A["split_fp16"] and eb <= TOL_B["split_fp16"]
     torch.cuda.synchronize()
     assert int(step.item()) == nsteps
+
+
+def test_output_offsets_beyond_int32(fem):
+    """p = 4 with 140000 elements: the output (2.19e9 entries, 8.75 GB) is indexed past 2^31;
+    elements on both sides of that boundary and the last one against the oracle."""
+    import oracle
+    import torch
+    base = synth.make(2, p=4, grid=(10, 10, 10))
+    reps = 140
+    geom = np.tile(base.geom, (reps, 1, 1))
+    coef = np.tile(base.coef, (reps, 1))
+    nel = geom.shape[0]
+    ns2 = 125 * 125
+    assert nel * ns2 > 2 ** 31
+    g, c = to_dev(geom, coef)
+    A = torch.empty((nel, 125, 125), dtype=torch.float32, device="cuda")
+    b = torch.empty((nel, 125), dtype=torch.float32, device="cuda")
+    fem.integrate(g, c, 4, precision="split_fp16", out_A=A, out_b=b)
+    torch.cuda.synchronize()
+    cross = 2 ** 31 // ns2
+    idx = np.array([0, cross - 1, cross, cross + 1, nel - 1])
+    Aref, bref, _ = oracle.integrate(geom[idx], coef[idx], p=4)
+    ti = torch.from_numpy(idx).cuda()
+    ea = rel_fro(A[ti].double().cpu().numpy(), Aref)
+    eb = rel_vec(b[ti].double().cpu().numpy(), bref)
+    log(f"[fullsize] p=4 nel={nel} entries={nel * ns2:.3e} errA max={ea.max():.3e} errb max={eb.max():.3e}")
+    assert ea.max() <= TOL_A["split_fp16"] and eb.max() <= TOL_B["split_fp16"]
+
+
+@pytest.mark.parametrize("scale", [1e-4, 1e4])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "split_fp16"])
+def test_extreme_element_sizes(fem, scale, prec):
+    """Meshes scaled by 1e-4 and 1e4 (detJ ~ 1e-12 and 1e12 per unit element): the per-element
+    power-of-two scaling keeps the split products in FP16 range, so relative errors hold."""
+    import oracle
+    import torch
+    w = synth.make(2, p=3, grid=(4, 3, 3))
+    geom = w.geom * scale
+    A_ref, b_ref, _ = oracle.integrate(geom, w.coef, p=3)
+    g, c = to_dev(geom, w.coef)
+    status = torch.zeros(2, dtype=torch.int32, device="cuda")
+    A, b = fem.integrate(g, c, 3, precision=prec, status=status)
+    torch.cuda.synchronize()
+    ea = rel_fro(A.double().cpu().numpy(), A_ref)
+    eb = rel_vec(b.double().cpu().numpy(), b_ref)
+    log(f"[fullsize] scale={scale:g} prec={prec} errA max={ea.max():.3e} errb max={eb.max():.3e}")
+    assert status.cpu().tolist() == [0, 0]
+    assert ea.max() <= TOL_A[prec] and eb.max() <= TOL_B[prec]
