@@ -27,7 +27,7 @@ template <> struct VariantCfg<2, MF_K16, 3> { using type = Cfg<4, 1, 4, 1, 1, 3,
 template <> struct VariantCfg<2, MF_K16, 4> { using type = Cfg<1, 1, 1, 1, 1, 3, 1, 2, 1, 1>; };
 template <> struct VariantCfg<2, MF_K16, 5> { using type = Cfg<2, 1, 1, 1, 2, 3, 1, 2, 1, 1>; };
 template <> struct VariantCfg<3, MF_K16, 0> { using type = Cfg<4, 1, 4, 2, 2, 3, 1, 2, 1, 1>; };
-template <> struct VariantCfg<3, MF_K16, 1> { using type = Cfg<1, 1, 1, 2, 2, 3, 1, 2, 1, 1>; };
+template <> struct VariantCfg<3, MF_K16, 1> { using type = Cfg<8, 1, 8, 2, 2, 2, 1, 1, 1, 1>; };
 template <> struct VariantCfg<3, MF_K16, 2> { using type = Cfg<4, 1, 4, 2, 2, 2, 1, 2, 1>; };
 template <> struct VariantCfg<3, MF_K16, 3> { using type = Cfg<4, 1, 4, 2, 2, 2, 2, 0, 1>; };
 template <> struct VariantCfg<3, MF_K16, 4> { using type = Cfg<4, 1, 4, 2, 2, 2, 1, 2, 1, 1>; };
@@ -200,8 +200,8 @@ int variants_p(int p)
 constexpr int default_variant(int p, int fam)
 {
     if (fam == MF_F64) return 0;
-    constexpr int k16[8] = {0, 2, 2, 4, 3, 2, 2, 2};
-    constexpr int f32[8] = {0, 3, 2, 3, 5, 2, 1, 2};
+    constexpr int k16[8] = {0, 2, 2, 1, 3, 2, 2, 2};
+    constexpr int f32[8] = {0, 3, 2, 1, 5, 2, 1, 2};
     return fam == MF_F32 ? f32[p] : k16[p];
 }
 constexpr int mixed_variant(int p, int fam)
