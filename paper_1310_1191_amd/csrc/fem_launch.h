@@ -42,14 +42,18 @@ template <> struct VariantCfg<5, MF_K16, 0> { using type = Cfg<1, 1, 4, 4, 1, 1,
 template <> struct VariantCfg<5, MF_K16, 1> { using type = Cfg<1, 1, 4, 4, 1, 1, 2, 0, 1>; };
 template <> struct VariantCfg<5, MF_K16, 2> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1>; };
 template <> struct VariantCfg<5, MF_K16, 3> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<5, MF_K16, 4> { using type = Cfg<1, 1, 4, 7, 2, 1, 1, 0, 1>; };
 template <> struct VariantCfg<6, MF_K16, 0> { using type = Cfg<1, 1, 4, 6, 1, 1, 2, 0, 0>; };
 template <> struct VariantCfg<6, MF_K16, 1> { using type = Cfg<1, 1, 4, 6, 1, 1, 2, 0, 1>; };
 template <> struct VariantCfg<6, MF_K16, 2> { using type = Cfg<1, 3, 1, 4, 4, 1, 1, 0, 1>; };
 template <> struct VariantCfg<6, MF_K16, 3> { using type = Cfg<1, 3, 1, 4, 4, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<6, MF_K16, 4> { using type = Cfg<1, 1, 4, 11, 1, 1, 1, 0, 1>; };
+template <> struct VariantCfg<6, MF_K16, 5> { using type = Cfg<1, 4, 1, 3, 4, 1, 1, 0, 1>; };
 template <> struct VariantCfg<7, MF_K16, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 2, 0, 0>; };
 template <> struct VariantCfg<7, MF_K16, 1> { using type = Cfg<1, 1, 4, 8, 1, 1, 2, 0, 1>; };
 template <> struct VariantCfg<7, MF_K16, 2> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1>; };
 template <> struct VariantCfg<7, MF_K16, 3> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<7, MF_K16, 4> { using type = Cfg<1, 1, 4, 8, 2, 1, 1, 0, 1>; };
 template <int P, int V> struct VariantCfg<P, MF_F32, V> { using type = typename VariantCfg<P, MF_K16, V>::type; };
 // -- FP64 (16-wide blocks) --
 template <> struct VariantCfg<1, MF_F64, 0> { using type = Cfg<8, 1, 4, 1, 1, 2, 2, 1, 0>; };
@@ -200,14 +204,14 @@ int variants_p(int p)
 constexpr int default_variant(int p, int fam)
 {
     if (fam == MF_F64) return 0;
-    constexpr int k16[8] = {0, 2, 2, 1, 3, 2, 2, 2};
-    constexpr int f32[8] = {0, 3, 2, 1, 5, 2, 1, 2};
+    constexpr int k16[8] = {0, 2, 2, 1, 3, 4, 4, 4};
+    constexpr int f32[8] = {0, 3, 2, 1, 5, 4, 4, 4};
     return fam == MF_F32 ? f32[p] : k16[p];
 }
 constexpr int mixed_variant(int p, int fam)
 {
     if (fam == MF_F64) return 0;
-    constexpr int m[8] = {0, 1, 3, 4, 3, 2, 1, 2};
+    constexpr int m[8] = {0, 1, 3, 4, 3, 4, 4, 4};
     return m[p];
 }
 
