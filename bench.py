@@ -123,14 +123,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="plain",
                     choices=["plain", "high", "mixed", "timestep", "poisson", "elasticity", "nojac",
-                             "staged"],
+                             "staged", "degree"],
                     help="plain: p = 2, 3, 4 at scale (the headline); high: p = 5, 6, 7 in every "
                          "precision; mixed: 200000 elements of degrees 1..7 with coefficient fields, "
                          "one launch against per-degree launches; timestep: 50 graph-replayed steps "
                          "of 100000 mixed-degree elements; poisson: p = 1; elasticity: the vector "
                          "model problem (linear elastostatics) for p = 2..7; nojac: supplied "
                          "per-point Jacobian terms against computed ones for p = 1..7; staged: the "
-                         "plain workload from and to pinned host memory, chunks over streams")
+                         "plain workload from and to pinned host memory, chunks over streams; degree: "
+                         "one degree's benchmark mesh (--degree) in --precision, for profilers")
+    ap.add_argument("--degree", type=int, default=4, help="degree of the 'degree' workload (1..7)")
     ap.add_argument("--nojac", action="store_true",
                     help="timestep workload: read per-point Jacobian terms written once before the "
                          "time loop instead of computing them in every step")
@@ -154,7 +156,7 @@ def main():
     if args.workload != "plain":
         line = {"high": bench_high, "mixed": bench_mixed, "timestep": bench_timestep,
                 "poisson": bench_poisson, "elasticity": bench_elasticity,
-                "nojac": bench_nojac, "staged": bench_staged}[args.workload](
+                "nojac": bench_nojac, "staged": bench_staged, "degree": bench_degree}[args.workload](
             args, torch, fem, synth, dev)
         print(json.dumps(line), flush=True)
         return
@@ -700,6 +702,32 @@ def bench_staged(args, torch, fem, synth, dev):
                                    "pinned host memory; pipelined = 16 chunks over 3 streams",
                        "serial_ms": round(tot["serial"], 3), "pipelined_ms": round(tot["pipelined"], 3)},
             "per_degree": res}
+
+
+DEGREE_GRIDS = {1: (128, 128, 64), 2: (64, 64, 64), 3: (64, 64, 32), 4: (64, 32, 32),
+                5: (32, 32, 16), 6: (32, 16, 16), 7: (16, 16, 16)}
+
+
+def bench_degree(args, torch, fem, synth, dev):
+    """One degree's benchmark mesh (the plain-method grids for p = 2..4, the high-order grids
+    for p = 5..7, 128x128x64 for p = 1) integrated --steps times in --precision with the
+    default tile: the single-kernel run that the counter profiles are taken on."""
+    p = args.degree
+    if not 1 <= p <= 7:
+        raise SystemExit("--degree must be 1..7")
+    w = synth.make(2, p=max(p, 2), grid=DEGREE_GRIDS[p]) if p <= 4 else synth.make(3, p=p)
+    g, c = torch.from_numpy(w.geom).to(dev), torch.from_numpy(w.coef).to(dev)
+    ns = (p + 1) ** 3
+    A = torch.empty((w.nel, ns, ns), dtype=fem.out_dtype(args.precision), device=dev)
+    b = torch.empty((w.nel, ns), dtype=fem.out_dtype(args.precision), device=dev)
+    ms = time_calls(torch, lambda: fem.integrate(g, c, p, precision=args.precision, out_A=A, out_b=b),
+                    args.steps, args.warmup)
+    fl = flops_per_element(p) * w.nel / (ms * 1e-3) / 1e12
+    return {"metric": "element matrices/s", "value": w.nel / (ms * 1e-3), "unit": "element matrices/s",
+            "n_gpus": 1, "higher_is_better": True, "dtype": args.precision, "data": "synthetic",
+            "config": {"workload": f"cdr-hex p={p} on {'x'.join(map(str, DEGREE_GRIDS[p]))} ({w.nel} elements)",
+                       "variant": fem.fem_get_variant(p, fem.PRECISIONS[args.precision])},
+            "ms_per_launch": round(ms, 4), "tflops": round(fl, 2)}
 
 
 if __name__ == "__main__":
