@@ -82,7 +82,11 @@ typedef enum {
  *                     element matrix is the 3 x 3 block matrix of Ns x Ns blocks
  *                     A[(i,s)][(k,r)] = sum_q c_ijkl d_l phi_r d_j phi_s w_q detJ_q (eq.
  *                     (sum_int)), stored out_A[e][i][k][s][r]; out_b[e][i][s] =
- *                     sum_q f_i phi_s w_q detJ_q. Both are 9 (3) times the scalar sizes. */
+ *                     sum_q f_i phi_s w_q detJ_q. Both are 9 (3) times the scalar sizes.
+ *                     The tensor's major symmetry makes block (k, i) the transpose of block
+ *                     (i, k); for most degrees the library integrates the blocks with i <= k
+ *                     and writes the others as transposed copies (equal up to rounding to
+ *                     integrating them). */
 typedef enum { FEM_COEF_ELEMENT = 0, FEM_COEF_FIELD = 1, FEM_COEF_ELASTIC = 2 } fem_coef_mode;
 
 /* Per-call description of the coefficients and of optional mixed-degree data. HOST struct,

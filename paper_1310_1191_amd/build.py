@@ -23,6 +23,7 @@ HIP_SOURCES = [
     "fem_mixed.hip",
     "fem_timestep.hip",
     "fem_jacobian.hip",
+    "fem_transpose.hip",
     "fem_staged.cpp",
     "fem_k_f64.hip",
     "fem_k_f32.hip",

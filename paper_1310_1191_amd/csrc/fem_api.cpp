@@ -17,6 +17,7 @@
 #include "fem_layout.h"
 #include "fem_tables.h"
 #include "fem_jacobian.h"
+#include "fem_transpose.h"
 #include "fem_mixed.h"
 
 namespace fem {
@@ -65,6 +66,12 @@ struct State {
 State g_state;
 std::mutex g_mutex;
 int64_t g_cus = 256;  // compute units of the device (persistent grids: CUs x resident WGs)
+// Elasticity: whether the lower blocks are copied as transposes of the upper ones (instead of
+// integrated), per degree, for the 16-bit contraction paths and for FP32 / FP64 (measured on
+// MI355X: the copy costs about one integration of a block at p = 4 on the split path, where
+// the ragged 125 x 125 blocks transpose slowest; p = 1 blocks are too small to pay).
+constexpr bool ELASTIC_SYM_K16[8] = {false, false, true, true, false, true, true, true};
+constexpr bool ELASTIC_SYM_WIDE[8] = {false, false, true, true, true, true, true, true};
 
 uint16_t bf16_bits_rne(float f)
 {
@@ -472,13 +479,17 @@ int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coef
     const hipStream_t s = (hipStream_t)stream;
     KArgs a = base_args(coeffs, geom, out_A, out_b);
     if (p > 0 && coeffs->mode == FEM_COEF_ELASTIC) {
-        // nine blocks (test component i, trial component k), one launch each, written with
-        // element strides 9 Ns^2 and 3 Ns; the load vector of component i comes with block (i, i)
+        // blocks (test component i, trial component k), one launch each, written with element
+        // strides 9 Ns^2 and 3 Ns; the load vector of component i comes with block (i, i). Where
+        // it pays, the blocks below the diagonal are the transposes of those above (major
+        // symmetry of c_ijkl) and are copied instead of integrated.
         a.nel = nel;
         set_degree(a, p, coeffs->precision);
         const int64_t nsq = a.a_stride, ns = a.b_stride;
+        const bool wide = coeffs->precision == FEM_FP64 || coeffs->precision == FEM_FP32;
+        const bool sym = wide ? ELASTIC_SYM_WIDE[p] : ELASTIC_SYM_K16[p];
         for (int i = 0; i < 3; ++i)
-            for (int k = 0; k < 3; ++k) {
+            for (int k = sym ? i : 0; k < 3; ++k) {
                 KArgs ab = a;
                 ab.comp_i = i;
                 ab.comp_k = k;
@@ -490,6 +501,8 @@ int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coef
                 ab.status = (i == 0 && k == 0) ? coeffs->status : nullptr;
                 if (dispatch(coeffs->precision, p, ab, s, g_cus) != hipSuccess) return FEM_EHIP;
             }
+        if (sym && transpose_elastic_blocks(out_A, coeffs->precision == FEM_FP64, nel, (int)ns, s, g_cus) != hipSuccess)
+            return FEM_EHIP;
         return FEM_OK;
     }
     if (p > 0) {

@@ -81,3 +81,21 @@ def test_elastic_mixed_degree_is_rejected(fem):
     cc = fem.make_coeffs("fp64", fem.ELASTIC, c)
     out = torch.empty(1, device="cuda")
     assert fem.fem_integrate(geom.shape[0], 0, g.data_ptr(), cc, out.data_ptr(), None, None) != fem.FEM_OK
+
+
+@pytest.mark.parametrize("p", [2, 4, 5])
+@pytest.mark.parametrize("prec", ["fp32", "split_fp16"])
+def test_elastic_blocks_are_transposes(fem, p, prec):
+    """Block (k, i) equals block (i, k) transposed (major symmetry of the isotropic tensor),
+    whether the library integrates it or copies it."""
+    import torch
+    geom, coef, *_ = elastic_case(p)
+    g, c = to_dev(geom, coef)
+    A, _ = fem.integrate(g, c, p, precision=prec, mode=fem.ELASTIC)
+    torch.cuda.synchronize()
+    A = A.double().cpu().numpy()
+    for i in range(3):
+        for k in range(i + 1, 3):
+            up, low = A[:, i, k], A[:, k, i].transpose(0, 2, 1)
+            err = np.linalg.norm(up - low, axis=(1, 2)) / np.linalg.norm(A.reshape(len(A), -1), axis=1)
+            assert err.max() <= TOL_A[prec], (i, k, err.max())
