@@ -61,7 +61,9 @@ template <> struct VariantCfg<2, MF_F64, 0> { using type = Cfg<2, 1, 4, 2, 1, 2,
 template <> struct VariantCfg<3, MF_F64, 0> { using type = Cfg<1, 1, 4, 4, 1, 2, 2, 0, 0>; };
 template <> struct VariantCfg<4, MF_F64, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 1, 0, 0>; };
 template <> struct VariantCfg<5, MF_F64, 0> { using type = Cfg<1, 1, 4, 7, 1, 1, 1, 0, 0>; };
+template <> struct VariantCfg<5, MF_F64, 1> { using type = Cfg<1, 1, 4, 14, 1, 1, 1, 0, 0>; };
 template <> struct VariantCfg<6, MF_F64, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 1, 0, 0>; };
+template <> struct VariantCfg<6, MF_F64, 1> { using type = Cfg<1, 1, 4, 11, 1, 1, 1, 0, 0>; };
 template <> struct VariantCfg<7, MF_F64, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 1, 0, 0>; };
 
 template <int P, int PREC, int V>
@@ -203,7 +205,8 @@ int variants_p(int p)
 // single-launch mixed-degree kernel (256-thread workgroups only).
 constexpr int default_variant(int p, int fam)
 {
-    if (fam == MF_F64) return 0;
+    constexpr int f64[8] = {0, 0, 0, 0, 0, 1, 1, 0};
+    if (fam == MF_F64) return f64[p];
     constexpr int k16[8] = {0, 2, 2, 1, 3, 4, 4, 4};
     constexpr int f32[8] = {0, 3, 2, 1, 5, 4, 4, 4};
     return fam == MF_F32 ? f32[p] : k16[p];
