@@ -258,7 +258,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(ach_bytes, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach_bytes / HBM_PEAK_GBS, 4)}
-    variant = fem.fem_get_variant(pd, fem.PRECISIONS[args.precision])
+    variant = fem.fem_get_variant(pd, fem.PRECISIONS[args.precision], fem.ELEMENT)
     roof["kernel"] = f"k_integrate p={pd} {args.precision} variant {variant}"
     roof["launch_ms"] = round(per_p[pd], 4)
     roof["traffic"] = measured_traffic(pd, args.precision, variant)
@@ -425,8 +425,9 @@ def bench_mixed(args, torch, fem, synth, dev):
         g, c, f, d, ws, a_off, b_off, A, b = mixed_buffers(torch, fem, w, dev, prec)
         a_np = a_off.cpu().numpy()
         code = fem.PRECISIONS[prec]
+        saved = fem.fem_get_variant(0, code, fem.FIELD)
         for strategy, name in ((0, "single_launch"), (1, "per_degree_launches")):
-            fem.fem_set_variant(0, code, strategy)
+            fem.fem_set_variant(0, code, fem.FIELD, strategy)
             call = lambda: fem.integrate_mixed(g, c, d, precision=prec, mode=fem.FIELD, field=f,
                                                a_off=a_off, b_off=b_off, out_A=A, out_b=b, workspace=ws)
             ms = time_calls(torch, call, max(3, args.steps // 4), 1)
@@ -435,7 +436,7 @@ def bench_mixed(args, torch, fem, synth, dev):
             res[f"{prec}/{name}"] = {"ms": round(ms, 3), "el_per_s": w.nel / (ms * 1e-3),
                                      "tflops": round(fl, 2), "max_rel_err_sample": max(errs)}
             log(f"[bench] mixed {prec} {name}: {ms:.3f} ms, {fl:.1f} TFLOP/s, max err {max(errs):.2e}")
-        fem.fem_set_variant(0, code, 0)
+        fem.fem_set_variant(0, code, fem.FIELD, saved)  # the strategy in force before the benchmark
         del A, b
         torch.cuda.empty_cache()
     best = min(res["split_fp16/single_launch"]["ms"], res["split_fp16/per_degree_launches"]["ms"])
@@ -726,7 +727,7 @@ def bench_degree(args, torch, fem, synth, dev):
     return {"metric": "element matrices/s", "value": w.nel / (ms * 1e-3), "unit": "element matrices/s",
             "n_gpus": 1, "higher_is_better": True, "dtype": args.precision, "data": "synthetic",
             "config": {"workload": f"cdr-hex p={p} on {'x'.join(map(str, DEGREE_GRIDS[p]))} ({w.nel} elements)",
-                       "variant": fem.fem_get_variant(p, fem.PRECISIONS[args.precision])},
+                       "variant": fem.fem_get_variant(p, fem.PRECISIONS[args.precision], fem.ELEMENT)},
             "ms_per_launch": round(ms, 4), "tflops": round(fl, 2)}
 
 

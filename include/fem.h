@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define FEM_ABI_VERSION 2
+#define FEM_ABI_VERSION 3
 
 typedef enum {
     FEM_OK = 0,
@@ -114,12 +114,18 @@ typedef struct fem_coeffs {
                                 writes them; any other source is taken as given. */
 } fem_coeffs;
 
-/* Make `device` current, build the FP64 reference tables for p = 1..7 (quadrature, 1-D
- * Lagrange values and derivatives, the B^T operand tables in every precision) and upload them.
- * Idempotent for the same device. Not thread-safe; call before any other function. */
+/* The set-up part of the host manager of section 4.2: make `device` current, query its
+ * properties (compute units, shared-memory limits; section 4.2 sizes the launch from them),
+ * build the FP64 reference tables for p = 1..7 (the arrays xi^Q, w^Q and phi^Q of section 2:
+ * quadrature, 1-D Lagrange values and derivatives, the B^T operand tables in every precision)
+ * and upload them once, so that later calls transfer no tables (section 4.2 keeps the shape
+ * function table in global memory). Idempotent for the same device; FEM_EINVAL for a second
+ * device. Not thread-safe; call before any other function. */
 int fem_init(int device);
 
-/* Release the tables. Afterwards every call but fem_init returns FEM_ENOTINIT. */
+/* The tear-down part of the host manager of section 4.2: synchronise the device and release
+ * the tables and staging buffers fem_init and fem_integrate_staged allocated. Afterwards every
+ * call but fem_init returns FEM_ENOTINIT. */
 int fem_finalize(void);
 
 /* Integrate nel elements (Algorithm 2 of section 2 for each element, all elements in parallel:
@@ -145,8 +151,8 @@ int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coef
 int fem_jacobian_terms(int64_t nel, int p, const double *geom, const int8_t *degree,
                        const int64_t *b_off, double *jac, void *stream);
 
-/* Host-resident meshes (the end-to-end view of section 6, where the paper times the transfer
- * of inputs, the kernel and the transfer of results): integrates nel elements of uniform degree
+/* Host-resident meshes (the end-to-end view of section 5.4, whose Tables 6 and 7 time the
+ * transfer of inputs, the kernel and the transfer of results separately): integrates nel elements of uniform degree
  * p whose data live in HOST memory, in chunks of `chunk` elements over `nstreams` streams
  * (1..FEM_STAGED_MAX_STREAMS). Chunk c goes to stream c mod nstreams as {copy geometry and
  * records to the device, fem_integrate, copy A and b back}; with more than one stream the
@@ -175,10 +181,14 @@ int fem_integrate_staged(int64_t nel, int p, const double *geom, const fem_coeff
                          void *out_A, void *out_b, int64_t chunk, int nstreams,
                          fem_staged_stats *stats);
 
-/* Bytes of device workspace that a mixed-degree fem_integrate over nel elements needs. */
+/* Bytes of device workspace that a mixed-degree fem_integrate over nel elements needs: the
+ * element ids classified by degree (section 4.2: the host manager splits the elements into
+ * sets of equal degree) and the partial sums of fem_mixed_offsets. 0 for nel < 0. */
 size_t fem_workspace_bytes(int64_t nel);
 
-/* Exclusive scans a_off[e] = sum_{e' < e} Ns(e')^2 and b_off[e] = sum_{e' < e} Ns(e') over a
+/* Output placement for a mesh of mixed degree (section 4.2: elements classified by degree; the
+ * unpadded element matrices of section 4.1 then lie back to back): exclusive scans
+ * a_off[e] = sum_{e' < e} Ns(e')^2 and b_off[e] = sum_{e' < e} Ns(e') over a
  * device degree array, nel + 1 entries each, computed on the device. `workspace` as for
  * fem_integrate. Degrees outside 1..7 count as 0 entries; fem_integrate skips such elements. */
 int fem_mixed_offsets(int64_t nel, const int8_t *degree, int64_t *a_off, int64_t *b_off,
@@ -216,40 +226,52 @@ int fem_reference_tables(int p, double *gauss_x, double *gauss_w, double *lobatt
  * default) issues one launch per degree, each with the variant chosen for that degree. */
 #define FEM_MAX_VARIANTS 6
 
-/* Number of variants compiled for (p, precision), p = 0..7 (>= 1), FEM_EDEGREE or FEM_EINVAL. */
+/* Number of variants compiled for (p, precision), p = 0..7 (>= 1), FEM_EDEGREE or FEM_EINVAL
+ * (the work-assignment parameters of section 4.2 as compiled alternatives). */
 int fem_variant_count(int p, int precision);
 
-/* The variant fem_integrate launches for (p, precision), or FEM_EDEGREE / FEM_EINVAL. */
-int fem_get_variant(int p, int precision);
+/* The variant fem_integrate launches for (p, precision, mode) (section 4.2: parameters chosen
+ * per degree), or FEM_EDEGREE / FEM_EINVAL. mode is a fem_coef_mode: the coefficient mode
+ * changes the per-point prologue, so each mode has its own choice. */
+int fem_get_variant(int p, int precision, int mode);
 
-/* Choose the variant for (p, precision); FEM_ECONFIG if variant >= fem_variant_count. Every
- * variant computes the same result to the precision's tolerance. */
-int fem_set_variant(int p, int precision, int variant);
+/* Choose the variant for (p, precision, mode) (section 4.2); FEM_ECONFIG if variant >=
+ * fem_variant_count. Every variant computes the same result to the precision's tolerance. */
+int fem_set_variant(int p, int precision, int mode, int variant);
 
 /* The variant (tile configuration) that the single-launch mixed-degree kernel uses for degree
- * p = 1..7 and precision; fixed at build time. FEM_EDEGREE / FEM_EINVAL on bad arguments. */
+ * p = 1..7 and precision (section 4.2: per-degree parameters inside the one launch over all
+ * degree classes); fixed at build time. FEM_EDEGREE / FEM_EINVAL on bad arguments. */
 int fem_mixed_variant(int p, int precision);
 
-/* Time every variant of (p, precision) on a seeded synthetic batch of nel elements (element
- * coefficients, mildly distorted cubes; for p = 0 degrees 1..7 drawn with weights 8 - p, and
- * the timed call includes the device bucketing; 1 warm-up and 5 timed calls each, on a stream
- * of its own), choose the fastest, and, if json_path is not NULL, record the choice and the times
- * in that HOST file (other entries of an existing file are kept). chosen (HOST, may be NULL)
- * receives the variant, times_ms (HOST [FEM_MAX_VARIANTS], may be NULL) the mean milliseconds
- * per launch of each variant. Allocates and frees device memory for the batch and
- * synchronises; not for use under stream capture. */
-int fem_autotune(int p, int precision, int64_t nel, const char *json_path, int *chosen,
+/* Choose the work assignment of (p, precision, mode) by measurement (section 4.2 derives the
+ * launch parameters per degree from the device's limits; here the compiled variants are timed
+ * instead): time every variant on a seeded synthetic batch of nel elements in coefficient mode
+ * `mode` (mildly distorted cubes; ELEMENT: CDR records, FIELD: rotations, loads and a seeded
+ * field descriptor, ELASTIC: E, nu and body forces; for p = 0 degrees 1..7 drawn with weights
+ * 8 - p, the timed call including the device bucketing; ELASTIC needs p >= 1; 1 warm-up and 5
+ * timed calls each, on a stream of its own), choose the fastest for (p, precision, mode), and,
+ * if json_path is not NULL, record the choice and the times in that HOST file, keyed by
+ * (architecture, p, precision, mode) (other entries of an existing file are kept). chosen
+ * (HOST, may be NULL) receives the variant, times_ms (HOST [FEM_MAX_VARIANTS], may be NULL)
+ * the mean milliseconds per call of each variant. Allocates and frees device memory for the
+ * batch and synchronises; not for use under stream capture. */
+int fem_autotune(int p, int precision, int mode, int64_t nel, const char *json_path, int *chosen,
                  double *times_ms);
 
-/* Apply the choices recorded in a file written by fem_autotune. FEM_ECONFIG if the file was
- * written on another GPU architecture; entries naming a variant that does not exist are
- * skipped. applied (HOST, may be NULL) receives the number of choices applied. */
+/* Apply the choices recorded in a file written by fem_autotune (section 4.2: per-degree launch
+ * parameters). FEM_ECONFIG if the file was written on another GPU architecture; entries naming
+ * a variant that does not exist are skipped. applied (HOST, may be NULL) receives the number of
+ * choices applied. */
 int fem_load_tuning(const char *json_path, int *applied);
 
-/* Static text for a status code. Never NULL. */
+/* Static text for a status code of the argument and device checks of the host manager
+ * (section 4.2). Never NULL. */
 const char *fem_strerror(int status);
 
-/* FEM_ABI_VERSION of the loaded library. */
+/* FEM_ABI_VERSION of the loaded library: the layout of fem_coeffs and of these calls (the
+ * operation, Algorithm 2 of section 2 in the arrangement of section 4, is the same in every
+ * version). */
 int fem_abi_version(void);
 
 #ifdef __cplusplus

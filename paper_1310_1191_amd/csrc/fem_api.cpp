@@ -65,6 +65,7 @@ struct State {
 };
 State g_state;
 std::mutex g_mutex;
+
 int64_t g_cus = 256;  // compute units of the device (persistent grids: CUs x resident WGs)
 // Elasticity: whether the lower blocks are copied as transposes of the upper ones (instead of
 // integrated), per degree, for the 16-bit contraction paths and for FP32 / FP64 (measured on
@@ -280,24 +281,26 @@ hipError_t dispatch_variant(int prec, int p, int v, const KArgs &a, hipStream_t 
     }
 }
 
-// The variant each (degree, precision) launches: the measured default until fem_set_variant,
-// fem_autotune or fem_load_tuning chooses another. Row 0: the mixed-degree strategy.
+// The variant each (degree, precision, coefficient mode) launches: the measured default until
+// fem_set_variant, fem_autotune or fem_load_tuning chooses another. Row 0: the mixed-degree
+// strategy.
+constexpr int NMODES = 3;
 struct Choices {
-    int v[8][5];
+    int v[8][5][NMODES];
     Choices()
     {
-        for (int prec = 0; prec < 5; ++prec) {
-            v[0][prec] = MIXED_PER_DEGREE;
-            for (int p = 1; p <= 7; ++p) v[p][prec] = default_variant(p, family_of(prec));
-        }
+        for (int prec = 0; prec < 5; ++prec)
+            for (int mode = 0; mode < NMODES; ++mode) {
+                v[0][prec][mode] = MIXED_PER_DEGREE;
+                for (int p = 1; p <= 7; ++p) v[p][prec][mode] = default_variant(p, family_of(prec));
+            }
     }
-    int *operator[](int p) { return v[p]; }
 };
 Choices g_choice;
 
-hipError_t dispatch(int prec, int p, const KArgs &a, hipStream_t s, int64_t cus)
+hipError_t dispatch(int prec, int mode, int p, const KArgs &a, hipStream_t s, int64_t cus)
 {
-    return dispatch_variant(prec, p, g_choice[p][prec], a, s, cus);
+    return dispatch_variant(prec, p, g_choice.v[p][prec][mode], a, s, cus);
 }
 
 hipError_t dispatch_mixed(int prec, const MixedKArgs &m, int64_t nel, hipStream_t s, int64_t cus)
@@ -499,7 +502,7 @@ int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coef
                 ab.b_stride = 3 * ns;
                 ab.out_b = (i == k) ? out_b : nullptr;
                 ab.status = (i == 0 && k == 0) ? coeffs->status : nullptr;
-                if (dispatch(coeffs->precision, p, ab, s, g_cus) != hipSuccess) return FEM_EHIP;
+                if (dispatch(coeffs->precision, FEM_COEF_ELASTIC, p, ab, s, g_cus) != hipSuccess) return FEM_EHIP;
             }
         if (sym && transpose_elastic_blocks(out_A, coeffs->precision == FEM_FP64, nel, (int)ns, s, g_cus) != hipSuccess)
             return FEM_EHIP;
@@ -508,7 +511,7 @@ int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coef
     if (p > 0) {
         a.nel = nel;
         set_degree(a, p, coeffs->precision);
-        return dispatch(coeffs->precision, p, a, s, g_cus) == hipSuccess ? FEM_OK : FEM_EHIP;
+        return dispatch(coeffs->precision, coeffs->mode, p, a, s, g_cus) == hipSuccess ? FEM_OK : FEM_EHIP;
     }
     // mixed degree: bucket on the device, then one launch per degree over its bucket
     if (!coeffs->a_off || ((out_b || coeffs->jac) && !coeffs->b_off)) return FEM_EINVAL;
@@ -526,10 +529,10 @@ int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coef
         ap.elist = plan.elist;
         ap.seg = plan.seg + 2 * pp;
     }
-    if (g_choice[0][coeffs->precision] == MIXED_SINGLE)
+    if (g_choice.v[0][coeffs->precision][coeffs->mode] == MIXED_SINGLE)
         return dispatch_mixed(coeffs->precision, m, nel, s, g_cus) == hipSuccess ? FEM_OK : FEM_EHIP;
     for (int pp = 7; pp >= 1; --pp)  // heaviest degree first
-        if (dispatch(coeffs->precision, pp, m.deg[pp - 1], s, g_cus) != hipSuccess) return FEM_EHIP;
+        if (dispatch(coeffs->precision, coeffs->mode, pp, m.deg[pp - 1], s, g_cus) != hipSuccess) return FEM_EHIP;
     return FEM_OK;
 }
 
@@ -537,17 +540,21 @@ int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coef
 
 namespace {
 
-// Seeded synthetic batch for fem_autotune: independent, mildly distorted unit cubes with an
-// anisotropic SPD diffusion, a small convection and a reaction term (element records), so that
-// every variant runs the same arithmetic it runs on a real mesh.
+// Seeded synthetic batch for fem_autotune: independent, mildly distorted unit cubes, with the
+// records of the tuned coefficient mode (ELEMENT: an anisotropic SPD diffusion, a small
+// convection and a reaction term; FIELD: a rotation and a load per element and a field
+// descriptor of 7 fields x 5 modes; ELASTIC: Young modulus, Poisson ratio and body force), so
+// that every variant runs the same arithmetic it runs on a real mesh.
 struct TuneBatch {
-    std::vector<double> geom, elem;
+    std::vector<double> geom, elem, field;
+    int reclen = 14;
 };
-TuneBatch tune_batch(int64_t nel)
+TuneBatch tune_batch(int64_t nel, int mode)
 {
     TuneBatch t;
+    t.reclen = mode == FEM_COEF_ELEMENT ? 14 : (mode == FEM_COEF_FIELD ? 10 : 5);
     t.geom.resize(size_t(nel) * 24);
-    t.elem.assign(size_t(nel) * 14, 0.0);
+    t.elem.assign(size_t(nel) * t.reclen, 0.0);
     uint64_t x = 0x9e3779b97f4a7c15ull;
     auto uni = [&x]() {  // xorshift64*, uniform in [-1, 1)
         x ^= x >> 12; x ^= x << 25; x ^= x >> 27;
@@ -557,11 +564,30 @@ TuneBatch tune_batch(int64_t nel)
         for (int v = 0; v < 8; ++v)
             for (int d = 0; d < 3; ++d)
                 t.geom[e * 24 + v * 3 + d] = double((v >> d) & 1) + 0.1 * uni();
-        double *r = &t.elem[e * 14];
-        r[0] = 1.0 + 0.2 * uni(); r[4] = 1.0 + 0.2 * uni(); r[8] = 1.0 + 0.2 * uni();
-        r[1] = r[3] = 0.1 * uni();
-        r[9] = 0.3 * uni(); r[10] = 0.3 * uni(); r[11] = 0.3 * uni();
-        r[12] = 1.0 + 0.5 * uni(); r[13] = uni();
+        double *r = &t.elem[e * t.reclen];
+        if (mode == FEM_COEF_ELEMENT) {
+            r[0] = 1.0 + 0.2 * uni(); r[4] = 1.0 + 0.2 * uni(); r[8] = 1.0 + 0.2 * uni();
+            r[1] = r[3] = 0.1 * uni();
+            r[9] = 0.3 * uni(); r[10] = 0.3 * uni(); r[11] = 0.3 * uni();
+            r[12] = 1.0 + 0.5 * uni(); r[13] = uni();
+        } else if (mode == FEM_COEF_FIELD) {
+            // rotation about the third axis by a random angle, then the load
+            const double a = 3.14159265358979 * uni(), c = std::cos(a), sn = std::sin(a);
+            r[0] = c; r[1] = -sn; r[3] = sn; r[4] = c; r[8] = 1.0;
+            r[9] = uni();
+        } else {
+            r[0] = 5.5 + 4.5 * uni(); r[1] = 0.3 + 0.1 * uni();
+            r[2] = uni(); r[3] = uni(); r[4] = uni();
+        }
+    }
+    if (mode == FEM_COEF_FIELD) {
+        t.field.resize(175);
+        for (int sm = 0; sm < 35; ++sm) {
+            double *f = &t.field[sm * 5];
+            f[0] = 0.2 * uni();
+            for (int k = 1; k <= 3; ++k) f[k] = double(int(2.5 * (uni() + 1.0)) - 2);
+            f[4] = 3.14159265358979 * (uni() + 1.0);
+        }
     }
     return t;
 }
@@ -579,13 +605,13 @@ const char *arch_name()
 }
 
 struct TuneEntry {
-    int p, precision, variant;
+    int p, precision, mode, variant;
     double ms[FEM_MAX_VARIANTS];
     int count;
 };
 
 // Entries of a tuning file. Each entry sits on a line of its own:
-//   {"p": 2, "precision": 4, "variant": 0, "ms": [0.91, 1.02, 1.10]},
+//   {"p": 2, "precision": 4, "mode": 0, "variant": 0, "ms": [0.91, 1.02, 1.10]},
 bool read_tuning(const char *path, std::string *arch, std::vector<TuneEntry> *out)
 {
     FILE *f = std::fopen(path, "r");
@@ -595,8 +621,8 @@ bool read_tuning(const char *path, std::string *arch, std::vector<TuneEntry> *ou
         char a[64];
         if (std::sscanf(line, " {\"arch\": \"%63[^\"]\"", a) == 1) *arch = a;
         TuneEntry t{};
-        if (std::sscanf(line, " {\"p\": %d, \"precision\": %d, \"variant\": %d", &t.p, &t.precision,
-                        &t.variant) == 3) {
+        if (std::sscanf(line, " {\"p\": %d, \"precision\": %d, \"mode\": %d, \"variant\": %d", &t.p,
+                        &t.precision, &t.mode, &t.variant) == 4) {
             const char *m = std::strstr(line, "\"ms\": [");
             if (m) {
                 m += 7;
@@ -622,8 +648,8 @@ bool write_tuning(const char *path, const std::string &arch, const std::vector<T
     std::fprintf(f, "{\"arch\": \"%s\", \"entries\": [\n", arch.c_str());
     for (size_t k = 0; k < es.size(); ++k) {
         const TuneEntry &t = es[k];
-        std::fprintf(f, "  {\"p\": %d, \"precision\": %d, \"variant\": %d, \"ms\": [", t.p, t.precision,
-                     t.variant);
+        std::fprintf(f, "  {\"p\": %d, \"precision\": %d, \"mode\": %d, \"variant\": %d, \"ms\": [", t.p,
+                     t.precision, t.mode, t.variant);
         for (int v = 0; v < t.count; ++v) std::fprintf(f, "%s%.6g", v ? ", " : "", t.ms[v]);
         std::fprintf(f, "]}%s\n", k + 1 < es.size() ? "," : "");
     }
@@ -643,19 +669,19 @@ int fem_variant_count(int p, int precision)
     return variant_count(precision, p);
 }
 
-int fem_get_variant(int p, int precision)
+int fem_get_variant(int p, int precision, int mode)
 {
     if (p < 0 || p > 7) return FEM_EDEGREE;
-    if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16) return FEM_EINVAL;
-    return g_choice[p][precision];
+    if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16 || mode < 0 || mode >= NMODES) return FEM_EINVAL;
+    return g_choice.v[p][precision][mode];
 }
 
-int fem_set_variant(int p, int precision, int variant)
+int fem_set_variant(int p, int precision, int mode, int variant)
 {
     if (p < 0 || p > 7) return FEM_EDEGREE;
-    if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16) return FEM_EINVAL;
+    if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16 || mode < 0 || mode >= NMODES) return FEM_EINVAL;
     if (variant < 0 || variant >= variant_count(precision, p)) return FEM_ECONFIG;
-    g_choice[p][precision] = variant;
+    g_choice.v[p][precision][mode] = variant;
     return FEM_OK;
 }
 
@@ -666,15 +692,18 @@ int fem_mixed_variant(int p, int precision)
     return mixed_variant(p, family_of(precision));
 }
 
-int fem_autotune(int p, int precision, int64_t nel, const char *json_path, int *chosen,
+int fem_autotune(int p, int precision, int mode, int64_t nel, const char *json_path, int *chosen,
                  double *times_ms)
 {
     if (!g_state.blob) return FEM_ENOTINIT;
     if (p < 0 || p > 7) return FEM_EDEGREE;
-    if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16 || nel <= 0) return FEM_EINVAL;
+    if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16 || nel <= 0 || mode < 0 || mode >= NMODES)
+        return FEM_EINVAL;
+    if (mode == FEM_COEF_ELASTIC && p == 0) return FEM_EINVAL;
     const int nv = variant_count(precision, p);
     const size_t osz = precision == FEM_FP64 ? 8 : 4;
-    const TuneBatch tb = tune_batch(nel);
+    const int64_t blocks = mode == FEM_COEF_ELASTIC ? 9 : 1, comps = mode == FEM_COEF_ELASTIC ? 3 : 1;
+    const TuneBatch tb = tune_batch(nel, mode);
     // p = 0: degrees 1..7 with weights 8 - p, interleaved; offsets by an exclusive scan
     std::vector<int8_t> deg;
     std::vector<int64_t> a_off(1, 0), b_off(1, 0);
@@ -691,10 +720,10 @@ int fem_autotune(int p, int precision, int64_t nel, const char *json_path, int *
             b_off.push_back(b_off.back() + ns);
         }
     } else {
-        a_off.push_back(nel * int64_t(ns_of(p)) * ns_of(p));
-        b_off.push_back(nel * int64_t(ns_of(p)));
+        a_off.push_back(nel * blocks * int64_t(ns_of(p)) * ns_of(p));
+        b_off.push_back(nel * comps * int64_t(ns_of(p)));
     }
-    void *d_geom = nullptr, *d_elem = nullptr, *d_A = nullptr, *d_b = nullptr;
+    void *d_geom = nullptr, *d_elem = nullptr, *d_field = nullptr, *d_A = nullptr, *d_b = nullptr;
     void *d_deg = nullptr, *d_aoff = nullptr, *d_boff = nullptr, *d_ws = nullptr;
     const size_t ws_bytes = p == 0 ? mixed_workspace_bytes(nel) : 0;
     hipStream_t s = nullptr;
@@ -702,12 +731,14 @@ int fem_autotune(int p, int precision, int64_t nel, const char *json_path, int *
     int rc = FEM_OK;
     double best_ms = 0.0;
     int best = 0;
-    TuneEntry entry{p, precision, 0, {}, nv};
+    TuneEntry entry{p, precision, mode, 0, {}, nv};
     auto fail = [&](int code) { if (rc == FEM_OK) rc = code; };
     if (hipMalloc(&d_geom, tb.geom.size() * 8) != hipSuccess ||
         hipMalloc(&d_elem, tb.elem.size() * 8) != hipSuccess ||
         hipMalloc(&d_A, size_t(a_off.back()) * osz) != hipSuccess ||
         hipMalloc(&d_b, size_t(b_off.back()) * osz) != hipSuccess)
+        fail(FEM_ENOMEM);
+    if (rc == FEM_OK && !tb.field.empty() && hipMalloc(&d_field, tb.field.size() * 8) != hipSuccess)
         fail(FEM_ENOMEM);
     if (rc == FEM_OK && p == 0 &&
         (hipMalloc(&d_deg, nel) != hipSuccess || hipMalloc(&d_aoff, a_off.size() * 8) != hipSuccess ||
@@ -720,6 +751,9 @@ int fem_autotune(int p, int precision, int64_t nel, const char *json_path, int *
         (hipMemcpy(d_geom, tb.geom.data(), tb.geom.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
          hipMemcpy(d_elem, tb.elem.data(), tb.elem.size() * 8, hipMemcpyHostToDevice) != hipSuccess))
         fail(FEM_EHIP);
+    if (rc == FEM_OK && d_field &&
+        hipMemcpy(d_field, tb.field.data(), tb.field.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+        fail(FEM_EHIP);
     if (rc == FEM_OK && p == 0 &&
         (hipMemcpy(d_deg, deg.data(), nel, hipMemcpyHostToDevice) != hipSuccess ||
          hipMemcpy(d_aoff, a_off.data(), a_off.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
@@ -728,21 +762,20 @@ int fem_autotune(int p, int precision, int64_t nel, const char *json_path, int *
     fem_coeffs c;
     std::memset(&c, 0, sizeof(c));
     c.precision = precision;
-    c.mode = FEM_COEF_ELEMENT;
+    c.mode = mode;
     c.elem = static_cast<const double *>(d_elem);
+    c.field = static_cast<const double *>(d_field);
     c.degree = static_cast<const int8_t *>(d_deg);
     c.a_off = static_cast<const int64_t *>(d_aoff);
     c.b_off = static_cast<const int64_t *>(d_boff);
     c.workspace = d_ws;
     c.workspace_bytes = ws_bytes;
-    KArgs a = base_args(&c, static_cast<const double *>(d_geom), d_A, d_b);
-    a.nel = nel;
-    if (p > 0) set_degree(a, p, precision);
-    const int saved = g_choice[p][precision];
+    const int saved = g_choice.v[p][precision][mode];
+    // each variant is timed through the whole call (every block of an elasticity call, the
+    // bucketing of a mixed-degree call)
     auto run = [&](int v) -> bool {
-        if (p > 0) return dispatch_variant(precision, p, v, a, s, g_cus) == hipSuccess;
-        g_choice[0][precision] = v;
-        return fem_integrate(nel, 0, static_cast<const double *>(d_geom), &c, d_A, d_b, s) == FEM_OK;
+        g_choice.v[p][precision][mode] = v;
+        return fem_integrate(nel, p, static_cast<const double *>(d_geom), &c, d_A, d_b, s) == FEM_OK;
     };
     constexpr int REPS = 5;
     for (int v = 0; v < nv && rc == FEM_OK; ++v) {
@@ -758,13 +791,13 @@ int fem_autotune(int p, int precision, int64_t nel, const char *json_path, int *
         if (times_ms) times_ms[v] = entry.ms[v];
         if (v == 0 || entry.ms[v] < best_ms) { best_ms = entry.ms[v]; best = v; }
     }
-    g_choice[p][precision] = saved;
+    g_choice.v[p][precision][mode] = saved;
     if (ev[0]) (void)hipEventDestroy(ev[0]);
     if (ev[1]) (void)hipEventDestroy(ev[1]);
     if (s) (void)hipStreamDestroy(s);
-    for (void *ptr : {d_geom, d_elem, d_A, d_b, d_deg, d_aoff, d_boff, d_ws}) (void)hipFree(ptr);
+    for (void *ptr : {d_geom, d_elem, d_field, d_A, d_b, d_deg, d_aoff, d_boff, d_ws}) (void)hipFree(ptr);
     if (rc != FEM_OK) return rc;
-    g_choice[p][precision] = best;
+    g_choice.v[p][precision][mode] = best;
     entry.variant = best;
     if (chosen) *chosen = best;
     if (json_path) {
@@ -772,7 +805,7 @@ int fem_autotune(int p, int precision, int64_t nel, const char *json_path, int *
         std::vector<TuneEntry> es, keep;
         read_tuning(json_path, &arch, &es);
         for (const TuneEntry &t : es)
-            if (!(t.p == p && t.precision == precision)) keep.push_back(t);
+            if (!(t.p == p && t.precision == precision && t.mode == mode)) keep.push_back(t);
         keep.push_back(entry);
         if (!write_tuning(json_path, arch_name(), keep)) return FEM_EINVAL;
     }
@@ -789,7 +822,7 @@ int fem_load_tuning(const char *json_path, int *applied)
     if (arch != arch_name()) return FEM_ECONFIG;
     int n = 0;
     for (const TuneEntry &t : es)
-        if (fem_set_variant(t.p, t.precision, t.variant) == FEM_OK) ++n;
+        if (fem_set_variant(t.p, t.precision, t.mode, t.variant) == FEM_OK) ++n;
     if (applied) *applied = n;
     return FEM_OK;
 }

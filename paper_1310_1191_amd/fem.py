@@ -95,10 +95,10 @@ def load():
     lib.fem_reference_tables.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp]
     lib.fem_field_advance.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
     lib.fem_variant_count.argtypes = [ctypes.c_int, ctypes.c_int]
-    lib.fem_get_variant.argtypes = [ctypes.c_int, ctypes.c_int]
-    lib.fem_set_variant.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
-    lib.fem_autotune.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_char_p,
-                                 ctypes.POINTER(ctypes.c_int), dp]
+    lib.fem_get_variant.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.fem_set_variant.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.fem_autotune.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                 ctypes.c_char_p, ctypes.POINTER(ctypes.c_int), dp]
     lib.fem_load_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]
     lib.fem_mixed_variant.argtypes = [ctypes.c_int, ctypes.c_int]
     _lib = lib
@@ -194,26 +194,30 @@ def fem_variant_count(p: int, precision: int) -> int:
     return rc
 
 
-def fem_get_variant(p: int, precision: int) -> int:
-    rc = int(load().fem_get_variant(int(p), int(precision)))
+MODES = (ELEMENT, FIELD, ELASTIC)
+
+
+def fem_get_variant(p: int, precision: int, mode: int) -> int:
+    rc = int(load().fem_get_variant(int(p), int(precision), int(mode)))
     if rc < 0:
         raise FemError(rc, "fem_get_variant")
     return rc
 
 
-def fem_set_variant(p: int, precision: int, variant: int) -> None:
-    rc = int(load().fem_set_variant(int(p), int(precision), int(variant)))
+def fem_set_variant(p: int, precision: int, mode: int, variant: int) -> None:
+    rc = int(load().fem_set_variant(int(p), int(precision), int(mode), int(variant)))
     if rc != FEM_OK:
         raise FemError(rc, "fem_set_variant")
 
 
-def fem_autotune(p: int, precision: int, nel: int, json_path: str | None = None):
-    """Time every variant of (p, precision) on nel synthetic elements and choose the fastest.
-    Returns (chosen variant, [ms per launch of each variant])."""
+def fem_autotune(p: int, precision: int, mode: int, nel: int, json_path: str | None = None):
+    """Time every variant of (p, precision, mode) on nel synthetic elements and choose the
+    fastest. Returns (chosen variant, [ms per call of each variant])."""
     chosen = ctypes.c_int(-1)
     times = (ctypes.c_double * MAX_VARIANTS)()
     path = None if json_path is None else os.fsencode(json_path)
-    rc = int(load().fem_autotune(int(p), int(precision), int(nel), path, ctypes.byref(chosen), times))
+    rc = int(load().fem_autotune(int(p), int(precision), int(mode), int(nel), path,
+                                 ctypes.byref(chosen), times))
     if rc != FEM_OK:
         raise FemError(rc, "fem_autotune")
     return chosen.value, list(times)[:fem_variant_count(p, precision)]
@@ -252,11 +256,21 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def _check(t, dtype, name):
+def _check(t, dtype, name, shape=None, min_numel=None):
+    """A caller's buffer must be a contiguous device tensor of the kernel's element type and
+    size: the kernels write and read by computed offsets, so a short or mistyped buffer would be
+    accessed out of bounds. Raises ValueError before anything is launched."""
     if t is None:
         return
     if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
         raise ValueError(f"{name} must be a contiguous {dtype} device tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(f"{name} holds {t.numel()} entries, the call writes {min_numel}")
+
+
+RECORD_LENGTH = {ELEMENT: 14, FIELD: 10, ELASTIC: 5}
 
 
 def _stream(stream):
@@ -289,26 +303,41 @@ def out_dtype(precision):
     return torch.float64 if prec == FP64 else torch.float32
 
 
-def integrate(geom, elem, p: int, precision="split_bf16", mode: int = ELEMENT, field=None,
+def _check_inputs(torch, geom, elem, mode, nel, field, status, jac, jac_rows):
+    if mode not in RECORD_LENGTH:
+        raise ValueError(f"unknown coefficient mode {mode}")
+    _check(elem, torch.float64, "elem", shape=(nel, RECORD_LENGTH[mode]))
+    _check(geom, torch.float64, "geom", shape=(nel, 8, 3))
+    _check(field, torch.float64, "field", min_numel=175)
+    _check(status, torch.int32, "status", min_numel=2)
+    _check(jac, torch.float64, "jac", min_numel=None if jac_rows is None else jac_rows * 10)
+    if mode == FIELD and field is None:
+        raise ValueError("FIELD mode needs the field descriptor")
+
+
+def integrate(geom, elem, p: int, precision="split_fp16", mode: int = ELEMENT, field=None,
               out_A=None, out_b=None, status=None, with_b: bool = True, stream=None, jac=None):
     """Uniform degree p: returns (A [nel, Ns, Ns], b [nel, Ns] or None) on the device; for
     mode ELASTIC (elem [nel, 5] = E, nu, f1, f2, f3) A is [nel, 3, 3, Ns, Ns], b [nel, 3, Ns].
     ``jac`` ([nel, Ns, 10], see ``jacobian_terms``) supplies the Jacobian terms; ``geom`` may
     then be None outside FIELD mode."""
     torch = _torch()
+    if not 1 <= p <= 7:
+        raise ValueError(f"degree {p} outside 1..7 (per-element degrees: integrate_mixed)")
     fem_init(elem.device.index or 0)
     nel = elem.shape[0]
-    ns = (p + 1) ** 3 if 1 <= p <= 7 else 0
+    ns = (p + 1) ** 3
     dt = out_dtype(precision)
-    _check(geom, torch.float64, "geom")
-    _check(elem, torch.float64, "elem")
-    _check(field, torch.float64, "field")
-    _check(jac, torch.float64, "jac")
+    _check_inputs(torch, geom, elem, mode, nel, field, status, jac, nel * ns)
+    if jac is not None:
+        _check(jac, torch.float64, "jac", shape=(nel, ns, 10))
     ashape, bshape = ((nel, 3, 3, ns, ns), (nel, 3, ns)) if mode == ELASTIC else ((nel, ns, ns), (nel, ns))
     if out_A is None:
         out_A = torch.empty(ashape, dtype=dt, device=elem.device)
     if out_b is None and with_b:
         out_b = torch.empty(bshape, dtype=dt, device=elem.device)
+    _check(out_A, dt, "out_A", min_numel=nel * (9 if mode == ELASTIC else 1) * ns * ns)
+    _check(out_b, dt, "out_b", min_numel=nel * (3 if mode == ELASTIC else 1) * ns)
     c = make_coeffs(precision, mode, elem, field=field, status=status, jac=jac)
     rc = fem_integrate(nel, p, _ptr(geom), c, _ptr(out_A), _ptr(out_b), _stream(stream))
     if rc != FEM_OK:
@@ -333,7 +362,7 @@ def mixed_offsets(degree, workspace=None, stream=None):
     return a_off, b_off
 
 
-def integrate_mixed(geom, elem, degree, precision="split_bf16", mode: int = ELEMENT, field=None,
+def integrate_mixed(geom, elem, degree, precision="split_fp16", mode: int = ELEMENT, field=None,
                     a_off=None, b_off=None, out_A=None, out_b=None, status=None, workspace=None,
                     with_b: bool = True, stream=None, jac=None):
     """Per-element degrees: returns (A packed, b packed, a_off, b_off) on the device. ``jac``
@@ -342,6 +371,13 @@ def integrate_mixed(geom, elem, degree, precision="split_bf16", mode: int = ELEM
     dev = elem.device
     fem_init(dev.index or 0)
     nel = elem.shape[0]
+    if mode == ELASTIC:
+        raise ValueError("the elasticity mode takes a uniform degree")
+    _check(degree, torch.int8, "degree", shape=(nel,))
+    _check_inputs(torch, geom, elem, mode, nel, field, status, None, None)
+    _check(a_off, torch.int64, "a_off", shape=(nel + 1,))
+    _check(b_off, torch.int64, "b_off", shape=(nel + 1,))
+    _check(workspace, torch.uint8, "workspace", min_numel=fem_workspace_bytes(nel))
     if workspace is None:
         workspace = torch.empty(fem_workspace_bytes(nel), dtype=torch.uint8, device=dev)
     if a_off is None or b_off is None:
@@ -353,6 +389,11 @@ def integrate_mixed(geom, elem, degree, precision="split_bf16", mode: int = ELEM
         out_A = torch.empty(int(a_off[-1].item()), dtype=dt, device=dev)
     if out_b is None and with_b:
         out_b = torch.empty(int(b_off[-1].item()), dtype=dt, device=dev)
+    # caller-provided outputs: type and contiguity only (their sizes follow from the device scans,
+    # which are not read back so that the call can be captured)
+    _check(out_A, dt, "out_A")
+    _check(out_b, dt, "out_b")
+    _check(jac, torch.float64, "jac")
     c = make_coeffs(precision, mode, elem, field=field, degree=degree, a_off=a_off, b_off=b_off,
                     status=status, workspace=workspace, jac=jac)
     rc = fem_integrate(nel, 0, _ptr(geom), c, _ptr(out_A), _ptr(out_b), _stream(stream))

@@ -4,7 +4,7 @@ This module only draws inputs. It holds none of the integration arithmetic and i
 from the HIP binding or from the oracle; both of those consume what it returns.
 
 The paper integrates model problems on meshes it does not publish and states that, for
-integration alone, the problem solved does not change the performance (section 5.3). These
+integration alone, the problem solved does not change the performance (section 5.4). These
 generators stand in for its workloads:
 
 * Domain [0,1]^3, structured nx x ny x nz grid, element e = i + nx (j + ny k).

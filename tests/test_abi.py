@@ -38,7 +38,7 @@ def test_binding_wraps_every_symbol():
 
 def test_host_only_calls(lib):
     from paper_1310_1191_amd import fem
-    assert fem.fem_abi_version() == 2
+    assert fem.fem_abi_version() == 3
     assert fem.fem_strerror(0) == "success"
     assert "init" in fem.fem_strerror(fem.FEM_ENOTINIT)
     assert fem.fem_strerror(-99) == "unknown status"
@@ -104,25 +104,31 @@ def test_reference_tables_reject_bad_degree():
 
 
 def test_variant_table_host_calls(lib):
-    """Variant counts and choices are host state: they need neither fem_init nor a GPU."""
+    """Variant counts and choices are host state: they need neither fem_init nor a GPU. Each
+    (degree, precision, coefficient mode) has its own choice."""
     from paper_1310_1191_amd import fem
     for p in range(1, 8):
         for prec in range(5):
             n = fem.fem_variant_count(p, prec)
             assert 1 <= n <= fem.MAX_VARIANTS
-            v0 = fem.fem_get_variant(p, prec)
-            assert 0 <= v0 < n
-            fem.fem_set_variant(p, prec, n - 1)
-            assert fem.fem_get_variant(p, prec) == n - 1
-            fem.fem_set_variant(p, prec, v0)
-            assert lib.fem_set_variant(p, prec, n) == fem.FEM_ECONFIG
-    for prec in range(5):  # p = 0: the mixed-degree strategies, per-degree launches by default
+            v0 = {m: fem.fem_get_variant(p, prec, m) for m in fem.MODES}
+            assert all(0 <= v < n for v in v0.values())
+            fem.fem_set_variant(p, prec, fem.FIELD, n - 1)
+            assert fem.fem_get_variant(p, prec, fem.FIELD) == n - 1
+            assert fem.fem_get_variant(p, prec, fem.ELEMENT) == v0[fem.ELEMENT]
+            assert fem.fem_get_variant(p, prec, fem.ELASTIC) == v0[fem.ELASTIC]
+            fem.fem_set_variant(p, prec, fem.FIELD, v0[fem.FIELD])
+            assert lib.fem_set_variant(p, prec, fem.ELEMENT, n) == fem.FEM_ECONFIG
+    for prec in range(5):  # p = 0: the mixed-degree strategies
         assert fem.fem_variant_count(0, prec) == 2
-        assert fem.fem_get_variant(0, prec) == 1
+        for m in fem.MODES:
+            assert fem.fem_get_variant(0, prec, m) in (0, 1)
     assert lib.fem_variant_count(-1, 0) == fem.FEM_EDEGREE
     assert lib.fem_variant_count(3, 5) == fem.FEM_EINVAL
-    assert lib.fem_set_variant(8, 0, 0) == fem.FEM_EDEGREE
-    assert lib.fem_autotune(3, 0, 100, None, None, None) == fem.FEM_ENOTINIT
+    assert lib.fem_set_variant(8, 0, 0, 0) == fem.FEM_EDEGREE
+    assert lib.fem_set_variant(3, 0, 3, 0) == fem.FEM_EINVAL
+    assert lib.fem_get_variant(3, 0, -1) == fem.FEM_EINVAL
+    assert lib.fem_autotune(3, 0, 0, 100, None, None, None) == fem.FEM_ENOTINIT
     assert lib.fem_load_tuning(b"/nonexistent.json", None) == fem.FEM_ENOTINIT
 
 
@@ -136,3 +142,72 @@ def test_variant_numbering_is_contiguous():
     assert seen
     for key, vs in seen.items():
         assert sorted(vs) == list(range(len(vs))), key
+
+
+def test_every_declaration_cites_the_paper():
+    """Each function declared in include/fem.h is preceded by a comment block that names the
+    passage of the paper it implements (a section, an algorithm, an equation or a table)."""
+    src = open(os.path.join(ROOT, "include", "fem.h")).read()
+    decls = list(re.finditer(r"^(?:int|size_t|const char \*)\s*(fem_\w+)\(", src, flags=re.M))
+    assert len(decls) >= 17
+    cite = re.compile(r"section \d|Algorithm \d|eq\. \(|Table \d", re.I)
+    prev_end = 0
+    for m in decls:
+        # the comments between the previous declaration and this one
+        comments = " ".join(re.findall(r"/\*.*?\*/", src[prev_end:m.start()], flags=re.S))
+        assert comments, f"{m.group(1)} has no comment block"
+        assert cite.search(comments), f"{m.group(1)}: its comment cites no passage"
+        prev_end = m.end()
+
+
+class _FakeDeviceTensor:
+    """Stands in for a device tensor on a machine without a GPU: the binding's checks read only
+    these attributes."""
+
+    def __init__(self, shape, dtype, contiguous=True):
+        self.shape, self.dtype, self._contiguous = tuple(shape), dtype, contiguous
+        self.is_cuda = True
+
+    def is_contiguous(self):
+        return self._contiguous
+
+    def numel(self):
+        n = 1
+        for s in self.shape:
+            n *= s
+        return n
+
+
+def test_binding_rejects_mis_sized_buffers():
+    """The binding refuses outputs and inputs whose type, contiguity, shape or size differ from
+    what the kernels index, before anything is launched (ValueError, no library call)."""
+    import torch
+    from paper_1310_1191_amd import fem
+    T = _FakeDeviceTensor
+    nel, ns = 10, 27
+    ok_elem, ok_geom = T((nel, 14), torch.float64), T((nel, 8, 3), torch.float64)
+    fem._check_inputs(torch, ok_geom, ok_elem, fem.ELEMENT, nel, None, None, None, None)
+    bad = [
+        dict(geom=T((nel, 8, 2), torch.float64)),                 # wrong geometry shape
+        dict(elem=T((nel, 10), torch.float64)),                   # FIELD-width record in ELEMENT mode
+        dict(elem=T((nel, 14), torch.float32)),                   # wrong dtype
+        dict(elem=T((nel, 14), torch.float64, contiguous=False)),
+        dict(status=T((1,), torch.int32)),                        # status needs 2 counters
+        dict(status=T((2,), torch.int64)),
+        dict(jac=T((nel * ns - 1, 10), torch.float64), rows=nel * ns),
+    ]
+    for b in bad:
+        args = dict(geom=ok_geom, elem=ok_elem, status=None, jac=None, rows=None)
+        args.update(b)
+        with pytest.raises(ValueError):
+            fem._check_inputs(torch, args["geom"], args["elem"], fem.ELEMENT, nel, None,
+                              args["status"], args["jac"], args["rows"])
+    with pytest.raises(ValueError):  # FIELD mode without its descriptor
+        fem._check_inputs(torch, ok_geom, T((nel, 10), torch.float64), fem.FIELD, nel, None, None, None, None)
+    # outputs: the element matrices of every element must fit
+    fem._check(T((nel, ns, ns), torch.float32), torch.float32, "out_A", min_numel=nel * ns * ns)
+    for t in (T((nel, ns, ns - 1), torch.float32), T((nel, ns, ns), torch.float64)):
+        with pytest.raises(ValueError):
+            fem._check(t, torch.float32, "out_A", min_numel=nel * ns * ns)
+    with pytest.raises(ValueError):  # a host tensor is not a device buffer
+        fem._check(torch.zeros(3), torch.float32, "out_b")

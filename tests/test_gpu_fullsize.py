@@ -115,7 +115,7 @@ def test_mixed_degree_full_size(fem, prec):
     idx = sample(w.nel, 24, 7)
     ea, eb = packed_errors(A, b, a_off.cpu().numpy(), b_off.cpu().numpy(), w, idx,
                            oracle_field_sample(w, w.field, idx))
-    log(f"[fullsize] mixed prec={prec} nel={w.nel} strategy={fem.fem_get_variant(0, fem.PRECISIONS[prec])} "
+    log(f"[fullsize] mixed prec={prec} nel={w.nel} strategy={fem.fem_get_variant(0, fem.PRECISIONS[prec], fem.FIELD)} "
         f"errA max={ea:.3e} errb max={eb:.3e}")
     assert ea <= TOL_A[prec] and eb <= TOL_B[prec]
 

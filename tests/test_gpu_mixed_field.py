@@ -62,14 +62,14 @@ def test_mixed_degree_field_parity(fem, field_case, prec, strategy):
     g, c, f, d = to_dev(w.geom, w.coef, w.field, w.degree)
     status = torch.zeros(2, dtype=torch.int32, device="cuda")
     code = fem.PRECISIONS[prec]
-    saved = fem.fem_get_variant(0, code)
-    fem.fem_set_variant(0, code, strategy)
+    saved = fem.fem_get_variant(0, code, fem.FIELD)
+    fem.fem_set_variant(0, code, fem.FIELD, strategy)
     try:
         A, b, a_off, b_off = fem.integrate_mixed(g, c, d, precision=prec, mode=fem.FIELD, field=f,
                                                  status=status)
         torch.cuda.synchronize()
     finally:
-        fem.fem_set_variant(0, code, saved)
+        fem.fem_set_variant(0, code, fem.FIELD, saved)
     np.testing.assert_array_equal(a_off.cpu().numpy(), a_ref_off)
     Ag, bg = split_packed(A.double().cpu().numpy(), b.double().cpu().numpy(), a_ref_off,
                           b_ref_off, w.degree)
@@ -129,18 +129,18 @@ def test_single_launch_equals_per_degree_launches_bitwise(fem, prec):
     w = synth.make(4, grid=(16, 12, 10))        # 1920 elements, degrees 1..7
     g, c, f, d = to_dev(w.geom, w.coef, w.field, w.degree)
     code = fem.PRECISIONS[prec]
-    saved = {p: fem.fem_get_variant(p, code) for p in range(8)}
+    saved = {p: fem.fem_get_variant(p, code, fem.FIELD) for p in range(8)}
     # per-degree launches with the tiles the single launch uses for each degree
     for p in range(1, 8):
-        fem.fem_set_variant(p, code, fem.mixed_tile_variant(p, code))
+        fem.fem_set_variant(p, code, fem.FIELD, fem.mixed_tile_variant(p, code))
     out = []
     for strategy in (0, 1):
-        fem.fem_set_variant(0, code, strategy)
+        fem.fem_set_variant(0, code, fem.FIELD, strategy)
         A, b, a_off, b_off = fem.integrate_mixed(g, c, d, precision=prec, mode=fem.FIELD, field=f)
         torch.cuda.synchronize()
         out.append((A, b))
     for p, v in saved.items():
-        fem.fem_set_variant(p, code, v)
+        fem.fem_set_variant(p, code, fem.FIELD, v)
     log(f"[mixed] {prec}: single vs per-degree, {w.nel} elements")
     assert torch.equal(out[0][0], out[1][0])
     assert torch.equal(out[0][1], out[1][1])

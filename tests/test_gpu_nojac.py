@@ -137,14 +137,14 @@ def test_supplied_terms_mixed_degree(fem, prec, strategy):
     a_off, b_off = fem.mixed_offsets(d)
     jt = fem.jacobian_terms(g, 0, degree=d, b_off=b_off)
     code = fem.PRECISIONS[prec]
-    saved = fem.fem_get_variant(0, code)
-    fem.fem_set_variant(0, code, strategy)
+    saved = fem.fem_get_variant(0, code, fem.FIELD)
+    fem.fem_set_variant(0, code, fem.FIELD, strategy)
     try:
         A, b, _, _ = fem.integrate_mixed(g, c, d, precision=prec, mode=fem.FIELD, field=f,
                                          a_off=a_off, b_off=b_off, jac=jt)
         torch.cuda.synchronize()
     finally:
-        fem.fem_set_variant(0, code, saved)
+        fem.fem_set_variant(0, code, fem.FIELD, saved)
     A = A.double().cpu().numpy()
     b = b.double().cpu().numpy()
     ea = max(rel_fro(A[a_ref[e]:a_ref[e + 1]].reshape(1, -1, 1),

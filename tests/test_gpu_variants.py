@@ -18,10 +18,10 @@ def fem():
     assert torch.cuda.is_available(), "no GPU visible"
     from paper_1310_1191_amd import fem as F
     F.fem_init(0)
-    saved = {(p, c): F.fem_get_variant(p, c) for p in range(8) for c in range(5)}
+    saved = {(p, c, m): F.fem_get_variant(p, c, m) for p in range(8) for c in range(5) for m in F.MODES}
     yield F
-    for (p, c), v in saved.items():
-        F.fem_set_variant(p, c, v)
+    for (p, c, m), v in saved.items():
+        F.fem_set_variant(p, c, m, v)
 
 
 @pytest.mark.parametrize("p", range(1, 8))
@@ -34,10 +34,10 @@ def test_every_variant_parity(fem, p, prec):
     geom, coef, A_ref, b_ref, _ = oracle_uniform(p)
     g, c = to_dev(geom, coef)
     first = None
-    v_default = fem.fem_get_variant(p, code)
+    v_default = fem.fem_get_variant(p, code, fem.ELEMENT)
     for v in range(n):
-        fem.fem_set_variant(p, code, v)
-        assert fem.fem_get_variant(p, code) == v
+        fem.fem_set_variant(p, code, fem.ELEMENT, v)
+        assert fem.fem_get_variant(p, code, fem.ELEMENT) == v
         status = torch.zeros(2, dtype=torch.int32, device="cuda")
         A, b = fem.integrate(g, c, p, precision=prec, status=status)
         torch.cuda.synchronize()
@@ -50,38 +50,47 @@ def test_every_variant_parity(fem, p, prec):
             first = bn
         else:  # the load vector does not depend on the tile configuration
             np.testing.assert_array_equal(bn, first)
-    fem.fem_set_variant(p, code, v_default)
+    fem.fem_set_variant(p, code, fem.ELEMENT, v_default)
 
 
 def test_set_variant_rejects_missing_variant(fem):
     for p in range(1, 8):
         n = fem.fem_variant_count(p, fem.FP64)
         with pytest.raises(fem.FemError):
-            fem.fem_set_variant(p, fem.FP64, n)
+            fem.fem_set_variant(p, fem.FP64, fem.ELEMENT, n)
 
 
 def test_autotune_writes_and_reloads_choice(fem, tmp_path):
+    """Tuning per (degree, precision, coefficient mode): ELEMENT, FIELD and ELASTIC batches, the
+    mixed-degree strategy, the JSON file keyed by mode, and its reload."""
     path = tmp_path / "tuning.json"
     seen = {}
-    saved = {(p, c): fem.fem_get_variant(p, c) for p in range(8) for c in range(5)}
-    for p, prec in [(2, fem.SPLIT_FP16), (4, fem.SPLIT_FP16), (3, fem.FP64), (0, fem.SPLIT_FP16)]:
-        v, times = fem.fem_autotune(p, prec, 3000, str(path))
-        log(f"[autotune] p={p} prec={prec} chosen={v} ms={times}")
+    saved = {(p, c, m): fem.fem_get_variant(p, c, m) for p in range(8) for c in range(5) for m in fem.MODES}
+    cases = [(2, fem.SPLIT_FP16, fem.ELEMENT), (4, fem.SPLIT_FP16, fem.ELEMENT), (3, fem.FP64, fem.ELEMENT),
+             (0, fem.SPLIT_FP16, fem.ELEMENT), (3, fem.SPLIT_FP16, fem.FIELD), (0, fem.FP32, fem.FIELD),
+             (2, fem.SPLIT_FP16, fem.ELASTIC)]
+    for p, prec, mode in cases:
+        other = {m: fem.fem_get_variant(p, prec, m) for m in fem.MODES if m != mode}
+        v, times = fem.fem_autotune(p, prec, mode, 3000 if mode != fem.ELASTIC else 1000, str(path))
+        log(f"[autotune] p={p} prec={prec} mode={mode} chosen={v} ms={times}")
         assert 0 <= v < fem.fem_variant_count(p, prec)
         assert len(times) == fem.fem_variant_count(p, prec) and min(times) > 0
         assert times[v] == min(times)
-        assert fem.fem_get_variant(p, prec) == v
-        seen[(p, prec)] = v
+        assert fem.fem_get_variant(p, prec, mode) == v
+        assert {m: fem.fem_get_variant(p, prec, m) for m in other} == other  # other modes untouched
+        seen[(p, prec, mode)] = v
     doc = json.loads(path.read_text())
-    got = {(e["p"], e["precision"]): e["variant"] for e in doc["entries"]}
+    got = {(e["p"], e["precision"], e["mode"]): e["variant"] for e in doc["entries"]}
     assert got == seen
-    for (p, prec) in seen:
-        fem.fem_set_variant(p, prec, (seen[(p, prec)] + 1) % fem.fem_variant_count(p, prec))
+    for (p, prec, mode) in seen:
+        fem.fem_set_variant(p, prec, mode, (seen[(p, prec, mode)] + 1) % fem.fem_variant_count(p, prec))
     assert fem.fem_load_tuning(str(path)) == len(seen)
-    for (p, prec), v in seen.items():
-        assert fem.fem_get_variant(p, prec) == v
-    for (p, c), v in saved.items():
-        fem.fem_set_variant(p, c, v)
+    for (p, prec, mode), v in seen.items():
+        assert fem.fem_get_variant(p, prec, mode) == v
+    with pytest.raises(fem.FemError):  # the elasticity mode takes a uniform degree
+        fem.fem_autotune(0, fem.SPLIT_FP16, fem.ELASTIC, 100)
+    for (p, c, m), v in saved.items():
+        fem.fem_set_variant(p, c, m, v)
 
 
 @pytest.mark.parametrize("p", range(1, 8))
@@ -94,10 +103,10 @@ def test_every_variant_field_mode(fem, p):
     A_ref, b_ref, _ = oracle.integrate(w.geom, w.coef, p=p, mode=oracle.FIELD, field=w.field)
     g, c, f = (torch.from_numpy(x).cuda() for x in (w.geom, w.coef, w.field))
     code = fem.SPLIT_FP16
-    v_default = fem.fem_get_variant(p, code)
+    v_default = fem.fem_get_variant(p, code, fem.FIELD)
     try:
         for v in range(fem.fem_variant_count(p, code)):
-            fem.fem_set_variant(p, code, v)
+            fem.fem_set_variant(p, code, fem.FIELD, v)
             A, b = fem.integrate(g, c, p, precision="split_fp16", mode=fem.FIELD, field=f)
             torch.cuda.synchronize()
             ea = rel_fro(A.double().cpu().numpy(), A_ref)
@@ -105,4 +114,4 @@ def test_every_variant_field_mode(fem, p):
             log(f"[variant FIELD] p={p} v={v} errA max={ea.max():.3e} errb max={eb.max():.3e}")
             assert ea.max() <= TOL_A["split_fp16"] and eb.max() <= TOL_B["split_fp16"]
     finally:
-        fem.fem_set_variant(p, code, v_default)
+        fem.fem_set_variant(p, code, fem.FIELD, v_default)
