@@ -49,7 +49,8 @@ typedef enum {
     FEM_ENOMEM = -4,     /* fem_init could not allocate its tables */
     FEM_EHIP = -5,       /* a HIP runtime call or kernel launch failed */
     FEM_ECONFIG = -6,    /* no compiled kernel configuration for the request */
-    FEM_EWORKSPACE = -7  /* workspace missing or smaller than fem_workspace_bytes() */
+    FEM_EWORKSPACE = -7, /* workspace missing or smaller than fem_workspace_bytes() */
+    FEM_ETOOBIG = -8     /* fem_integrate_noalloc: more elements than its static scratch holds */
 } fem_status;
 
 /* Arithmetic of the contraction A = B^T blockdiag(D_q) B. The Jacobian, its determinant and
@@ -140,6 +141,20 @@ int fem_finalize(void);
  * Outputs are double for FEM_FP64 and float otherwise. */
 int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coeffs, void *out_A,
                   void *out_b, void *stream);
+
+/* For callers that cannot allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc): fem_integrate with the same arguments, layouts and
+ * results, except that a mixed-degree call (p == 0) ignores coeffs->workspace and
+ * coeffs->workspace_bytes and uses a static device array of the library instead (one per device,
+ * about 16 MiB, held until the process ends, its address taken by fem_init). It allocates
+ * nothing, by any route. Limit: a mixed-degree call takes at most FEM_NOALLOC_MAX_NEL elements,
+ * more return FEM_ETOOBIG with nothing enqueued (uniform-degree calls need no scratch and take
+ * any nel). The array keeps the last call's contents; every call clears what it needs zeroed by
+ * a kernel of its own. All calls on one device share the one array, so mixed-degree calls that
+ * overlap on one device (concurrent streams, host threads) race; serialise them. */
+#define FEM_NOALLOC_MAX_NEL (1LL << 22)
+int fem_integrate_noalloc(int64_t nel, int p, const double *geom, const fem_coeffs *coeffs,
+                          void *out_A, void *out_b, void *stream);
 
 /* Jacobian terms for the NOJAC variant (section 4: the determinant and the 9 entries of the
  * inverse Jacobian of every element at every quadrature point, read by the integration instead

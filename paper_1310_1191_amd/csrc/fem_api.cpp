@@ -20,6 +20,8 @@
 #include "fem_transpose.h"
 #include "fem_mixed.h"
 
+static_assert(FEM_NOALLOC_MAX_NEL == fem::NOALLOC_MAX_NEL, "one element capacity of the static scratch");
+
 namespace fem {
 hipError_t prepare_f64();
 hipError_t prepare_f32();
@@ -63,6 +65,10 @@ struct State {
     void *blob = nullptr;  // one device allocation holding every table
     DegreeDev deg[8];
 };
+// Device address of the static mixed-degree scratch on each device fem_init has run on (taken
+// with that device current; every device holds its own copy of the array).
+constexpr int MAX_DEVICES = 64;
+void *g_scratch[MAX_DEVICES] = {};
 State g_state;
 std::mutex g_mutex;
 
@@ -389,6 +395,7 @@ const char *fem_strerror(int status)
     case FEM_EHIP: return "HIP runtime error";
     case FEM_ECONFIG: return "no kernel configuration for this request";
     case FEM_EWORKSPACE: return "workspace missing or too small";
+    case FEM_ETOOBIG: return "more elements than the static scratch of fem_integrate_noalloc holds (FEM_NOALLOC_MAX_NEL)";
     default: return "unknown status";
     }
 }
@@ -401,6 +408,11 @@ int fem_init(int device)
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return FEM_EINVAL;
     if (hipSetDevice(device) != hipSuccess) return FEM_EHIP;
+    if (device < MAX_DEVICES && !g_scratch[device]) {
+        void *ptr = nullptr;
+        if (mixed_scratch_address(&ptr) != hipSuccess || !ptr) return FEM_EHIP;
+        g_scratch[device] = ptr;
+    }
     hipError_t e;
     if ((e = prepare_f64()) != hipSuccess || (e = prepare_f32()) != hipSuccess ||
         (e = prepare_bf16()) != hipSuccess || (e = prepare_split_bf16()) != hipSuccess ||
@@ -464,8 +476,14 @@ int fem_mixed_offsets(int64_t nel, const int8_t *degree, int64_t *a_off, int64_t
                : FEM_EHIP;
 }
 
-int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coeffs, void *out_A,
-                  void *out_b, void *stream)
+}  // extern "C"
+
+namespace {
+
+// fem_integrate with the mixed-degree workspace given explicitly (the caller's, or the static
+// scratch of fem_integrate_noalloc).
+int integrate_impl(int64_t nel, int p, const double *geom, const fem_coeffs *coeffs, void *out_A,
+                   void *out_b, void *stream, void *workspace, size_t workspace_bytes)
 {
     if (!g_state.blob) return FEM_ENOTINIT;
     if (nel < 0 || !coeffs) return FEM_EINVAL;
@@ -515,9 +533,9 @@ int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coef
     }
     // mixed degree: bucket on the device, then one launch per degree over its bucket
     if (!coeffs->a_off || ((out_b || coeffs->jac) && !coeffs->b_off)) return FEM_EINVAL;
-    if (!coeffs->workspace || coeffs->workspace_bytes < mixed_workspace_bytes(nel)) return FEM_EWORKSPACE;
+    if (!workspace || workspace_bytes < mixed_workspace_bytes(nel)) return FEM_EWORKSPACE;
     MixedPlan plan;
-    if (mixed_bucket(nel, coeffs->degree, coeffs->workspace, s, &plan) != hipSuccess) return FEM_EHIP;
+    if (mixed_bucket(nel, coeffs->degree, workspace, s, &plan) != hipSuccess) return FEM_EHIP;
     a.a_off = coeffs->a_off;
     a.b_off = coeffs->b_off;
     MixedKArgs m;
@@ -534,6 +552,31 @@ int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coef
     for (int pp = 7; pp >= 1; --pp)  // heaviest degree first
         if (dispatch(coeffs->precision, coeffs->mode, pp, m.deg[pp - 1], s, g_cus) != hipSuccess) return FEM_EHIP;
     return FEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coeffs, void *out_A,
+                  void *out_b, void *stream)
+{
+    if (!coeffs) return FEM_EINVAL;
+    return integrate_impl(nel, p, geom, coeffs, out_A, out_b, stream, coeffs->workspace,
+                          coeffs->workspace_bytes);
+}
+
+int fem_integrate_noalloc(int64_t nel, int p, const double *geom, const fem_coeffs *coeffs,
+                          void *out_A, void *out_b, void *stream)
+{
+    if (!g_state.blob) return FEM_ENOTINIT;
+    if (!coeffs) return FEM_EINVAL;
+    if (p == 0 && nel > FEM_NOALLOC_MAX_NEL) return FEM_ETOOBIG;
+    const int dev = g_state.device;
+    void *ws = (dev >= 0 && dev < MAX_DEVICES) ? g_scratch[dev] : nullptr;
+    if (!ws) return FEM_ENOTINIT;
+    return integrate_impl(nel, p, geom, coeffs, out_A, out_b, stream, ws,
+                          mixed_workspace_bytes(FEM_NOALLOC_MAX_NEL));
 }
 
 }  // extern "C"

@@ -14,6 +14,10 @@ struct MixedPlan {
 
 size_t mixed_workspace_bytes(int64_t nel);
 hipError_t mixed_prepare();
+// Element capacity of the library's static device scratch (the workspace of the allocation-free
+// entry point) and the device address of that scratch on the current device.
+constexpr int64_t NOALLOC_MAX_NEL = int64_t(1) << 22;
+hipError_t mixed_scratch_address(void **ptr);
 // a_off[e] = sum_{e' < e} Ns(e')^2, b_off[e] = sum_{e' < e} Ns(e'), nel + 1 entries.
 hipError_t mixed_offsets(int64_t nel, const int8_t *degree, int64_t *a_off, int64_t *b_off,
                          void *workspace, hipStream_t s);

@@ -11,10 +11,17 @@ constexpr int64_t SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
 
 // Workspace layout (bytes): [0, 128) seg[8][2] int64; [256, 288) cursor[8] int32;
 // [512, ...) elist[nel] int32; then scan partials [2][nblocks] int64.
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-int64_t scan_blocks(int64_t nel) { return (nel + 1 + SCAN_TILE - 1) / SCAN_TILE; }
-size_t off_elist() { return 512; }
-size_t off_partials(int64_t nel) { return off_elist() + align256(size_t(nel) * 4); }
+constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr int64_t scan_blocks(int64_t nel) { return (nel + 1 + SCAN_TILE - 1) / SCAN_TILE; }
+constexpr size_t off_elist() { return 512; }
+constexpr size_t off_partials(int64_t nel) { return off_elist() + align256(size_t(nel) * 4); }
+constexpr size_t workspace_bytes(int64_t nel) { return off_partials(nel) + align256(size_t(scan_blocks(nel)) * 16); }
+
+// Workspace of the allocation-free entry point: one copy per device, held until the process
+// ends, sized for NOALLOC_MAX_NEL elements (about 16 MiB). Host code never passes this name to a
+// kernel (on the host it is only a stand-in for the symbol); it takes the device address from
+// mixed_scratch_address instead.
+static __device__ __align__(256) unsigned char scratch[workspace_bytes(NOALLOC_MAX_NEL)];
 
 __device__ inline int64_t ns_of_deg(int d)
 {
@@ -174,9 +181,12 @@ __global__ void k_tile_scan(int64_t nel, const int8_t *degree, const int64_t *pa
 
 }  // namespace
 
-size_t mixed_workspace_bytes(int64_t nel)
+size_t mixed_workspace_bytes(int64_t nel) { return workspace_bytes(nel); }
+
+hipError_t mixed_scratch_address(void **ptr)
 {
-    return off_partials(nel) + align256(size_t(scan_blocks(nel)) * 16);
+    *ptr = nullptr;
+    return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
 }
 
 hipError_t mixed_prepare() { return hipSuccess; }

@@ -20,6 +20,8 @@ FEM_ENOMEM = -4
 FEM_EHIP = -5
 FEM_ECONFIG = -6
 FEM_EWORKSPACE = -7
+FEM_ETOOBIG = -8
+NOALLOC_MAX_NEL = 1 << 22
 
 FP64, FP32, BF16, SPLIT_BF16, SPLIT_FP16 = 0, 1, 2, 3, 4
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "split_bf16": SPLIT_BF16,
@@ -81,6 +83,8 @@ def load():
     lib.fem_finalize.argtypes = []
     lib.fem_integrate.argtypes = [ctypes.c_int64, ctypes.c_int, vp, ctypes.POINTER(fem_coeffs), vp,
                                   vp, vp]
+    lib.fem_integrate_noalloc.argtypes = [ctypes.c_int64, ctypes.c_int, vp,
+                                          ctypes.POINTER(fem_coeffs), vp, vp, vp]
     lib.fem_workspace_bytes.argtypes = [ctypes.c_int64]
     lib.fem_workspace_bytes.restype = ctypes.c_size_t
     lib.fem_mixed_offsets.argtypes = [ctypes.c_int64, vp, vp, vp, vp, ctypes.c_size_t, vp]
@@ -110,7 +114,7 @@ def exported_symbols():
             "fem_mixed_offsets", "fem_field_advance", "fem_reference_tables", "fem_strerror",
             "fem_abi_version", "fem_variant_count", "fem_get_variant", "fem_set_variant",
             "fem_autotune", "fem_load_tuning", "fem_mixed_variant", "fem_jacobian_terms",
-            "fem_integrate_staged"]
+            "fem_integrate_staged", "fem_integrate_noalloc"]
 
 
 # ---------------------------------------------------------------------------------------------
@@ -158,6 +162,13 @@ def fem_integrate(nel: int, p: int, geom: int, coeffs: fem_coeffs, out_A: int, o
     """Raw call: integer device addresses, returns the status code."""
     return int(load().fem_integrate(int(nel), int(p), geom, ctypes.byref(coeffs), out_A, out_b,
                                     stream))
+
+
+def fem_integrate_noalloc(nel: int, p: int, geom: int, coeffs: fem_coeffs, out_A: int,
+                          out_b: int | None, stream: int | None) -> int:
+    """Raw call of the allocation-free variant: integer device addresses, returns the status."""
+    return int(load().fem_integrate_noalloc(int(nel), int(p), geom, ctypes.byref(coeffs), out_A,
+                                            out_b, stream))
 
 
 def fem_mixed_offsets(nel: int, degree: int, a_off: int, b_off: int, workspace: int,
