@@ -16,12 +16,13 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "fem_oracle.c")
+_SRC = [os.path.join(_HERE, "fem_oracle.c"), os.path.join(_HERE, "fem_oracle_prism.c")]
 _LIB_PATH = os.path.join(_HERE, "libfem_oracle.so")
 _lib = None
 
 ELEMENT = 0
 FIELD = 1
+ELASTIC = 2
 FLAG_DETJ = 1
 FLAG_NONFINITE = 2
 
@@ -34,7 +35,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         cmd = ["gcc", "-O3", "-march=native", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC",
-               "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+               "-shared", "-Wall", "-Wextra", "-o", tmp, *_SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -72,6 +73,13 @@ def _load():
         ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
     lib.oracle_max_threads.restype = ctypes.c_int
+    lib.oracle_prism_ns.argtypes = [ctypes.c_int]
+    lib.oracle_prism_shape.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, dp]
+    lib.oracle_integrate_prism.argtypes = [
+        ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_int]
     _lib = lib
     return lib
 
@@ -269,4 +277,49 @@ def integrate_elastic_nojac(jac, coef, p: int, threads: int = 0, with_b: bool = 
                                                _vp(flags), threads)
     if rc != 0:
         raise ValueError("oracle_integrate_elastic_nojac: bad arguments")
+    return A, b, flags
+
+
+# ---- prismatic elements (the reference element of section 2, Tables 1-2) ----
+def prism_ns(p: int) -> int:
+    return (p + 1) * (p + 1) * (p + 2) // 2
+
+
+def prism_shape(p: int, xi1: float, xi2: float, zeta: float):
+    """[Ns, 4]: value and reference derivatives of every prism shape function at one point."""
+    out = np.zeros((prism_ns(p), 4))
+    if _load().oracle_prism_shape(int(p), float(xi1), float(xi2), float(zeta), _dptr(out)) != 0:
+        raise ValueError("bad p")
+    return out
+
+
+def integrate_prism(geom, coef, p: int, mode: int = ELEMENT, field=None, threads: int = 0,
+                    with_b: bool = True, tri=None):
+    """Integrate prisms in FP64 (geom [nel, 6, 3]). ELEMENT / FIELD: (A [nel, Ns, Ns],
+    b [nel, Ns], flags); ELASTIC (coef [nel, 5]): (A [nel, 3, 3, Ns, Ns], b [nel, 3, Ns], flags).
+    The triangle rule is the oracle's own (prism_rule.triangle_rule) unless ``tri`` is given."""
+    from . import prism_rule
+    geom = np.ascontiguousarray(geom, dtype=np.float64)
+    coef = np.ascontiguousarray(coef, dtype=np.float64)
+    nel = geom.shape[0]
+    assert geom.shape[1:] == (6, 3)
+    rec = {ELEMENT: 14, FIELD: 10, ELASTIC: 5}[mode]
+    assert coef.shape == (nel, rec)
+    if tri is None:
+        pts, w = prism_rule.triangle_rule(p)
+        tri = np.column_stack([pts, w])
+    tri = np.ascontiguousarray(tri, dtype=np.float64)
+    fld = None
+    if mode == FIELD:
+        fld = np.ascontiguousarray(field, dtype=np.float64).reshape(-1)
+        assert fld.size == 175
+    ns = prism_ns(p) if 1 <= p <= 7 else 1
+    blk, comp = (9, 3) if mode == ELASTIC else (1, 1)
+    A = np.zeros((nel, 3, 3, ns, ns) if mode == ELASTIC else (nel, ns, ns))
+    b = (np.zeros((nel, 3, ns) if mode == ELASTIC else (nel, ns))) if with_b else None
+    flags = np.zeros(nel, dtype=np.int32)
+    rc = _load().oracle_integrate_prism(nel, p, _vp(geom), mode, _vp(coef), _vp(fld),
+                                        tri.shape[0], _vp(tri), _vp(A), _vp(b), _vp(flags), threads)
+    if rc != 0:
+        raise ValueError("oracle_integrate_prism: bad arguments")
     return A, b, flags

@@ -39,6 +39,7 @@ extern "C" {
 
 #define ORACLE_COEF_ELEMENT 0
 #define ORACLE_COEF_FIELD 1
+#define ORACLE_COEF_ELASTIC 2 /* prisms: the elastostatics of section 5.1, records [5] */
 #define ORACLE_FLAG_DETJ 1     /* detJ <= 0 at one or more quadrature points */
 #define ORACLE_FLAG_NONFINITE 2 /* non-finite input or output */
 
@@ -103,6 +104,33 @@ int oracle_integrate_nojac(int64_t nel, int p, const int8_t *degree, const doubl
 /* oracle_integrate_elastic with the Jacobian terms read from jac ([nel][Ns][10]). */
 int oracle_integrate_elastic_nojac(int64_t nel, int p, const double *jac, const double *coef,
                                    double *out_A, double *out_b, int32_t *flags, int nthreads);
+
+/* ---- prismatic elements (fem_oracle_prism.c; the reference element of section 2, Tables 1-2) ----
+ * Reference prism T x [-1,1] (T the unit right triangle), vertices v = t + 3h (triangle vertex t at
+ * (0,0), (1,0), (0,1); h = 0 bottom, zeta = -1; h = 1 top), geometry linear in the triangle and in
+ * zeta. Shape function i = t + Nt c: Lagrange basis of the degree-p polynomials on the triangle's
+ * principal lattice (node t = (a/p, b/p), a + b <= p, b outer, a inner) times the 1-D Lagrange
+ * polynomial of GLL node c in zeta; Ns = (p+1)^2 (p+2)/2. Quadrature point q = qt + ntq qz: the
+ * caller's triangle rule tri[ntq][3] = (xi1, xi2, weight) times the (p+1)-point Gauss-Legendre
+ * rule in zeta. */
+
+/* Ns of the degree-p prism, or -1. */
+int oracle_prism_ns(int p);
+
+/* phi[i][0..3] = value and reference derivatives (d/dxi1, d/dxi2, d/dzeta) of every prism shape
+ * function at one point. Returns 0, or -1 on a bad argument. */
+int oracle_prism_shape(int p, double xi1, double xi2, double zeta, double *phi);
+
+/* Integrate nel prisms of degree p (Algorithm 2 of section 2, eq. (sum_int) of section 5.1).
+ *   geom  [nel][6][3]
+ *   mode  ORACLE_COEF_ELEMENT (coef [nel][14]), ORACLE_COEF_FIELD (coef [nel][10], field [175])
+ *         or ORACLE_COEF_ELASTIC (coef [nel][5] = E, nu, f1, f2, f3)
+ *   out_A [nel][Ns][Ns] (elastostatics: [nel][3][3][Ns][Ns], block (i, k) = test component i,
+ *         trial component k); out_b [nel][Ns] ([nel][3][Ns]), may be NULL
+ * Returns 0, or -1 on an argument error. */
+int oracle_integrate_prism(int64_t nel, int p, const double *geom, int mode, const double *coef,
+                           const double *field, int ntq, const double *tri, double *out_A,
+                           double *out_b, int32_t *flags, int nthreads);
 
 /* Number of OpenMP threads a call with nthreads = 0 uses. */
 int oracle_max_threads(void);
