@@ -142,6 +142,30 @@ int fem_finalize(void);
 int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coeffs, void *out_A,
                   void *out_b, void *stream);
 
+/* Prismatic elements: the reference element of section 2 of the paper (Tables 1 and 2), the
+ * prism T x [-1,1], T = {xi1, xi2 >= 0, xi1 + xi2 <= 1}, with shape functions i = t + Nt c
+ * (Nt = (p+1)(p+2)/2, Ns = Nt (p+1): 6, 18, 40, 75, 126, 196, 288 for p = 1..7 as in Table 1):
+ * the Lagrange basis of the complete degree-p polynomials on the triangle's principal lattice
+ * (node t = (a/p, b/p), a + b <= p, b outer, a inner) times the 1-D Lagrange polynomial of GLL
+ * node c in zeta. Quadrature (Table 1's N_Q = 6, 18, 48, 80, 150, 231, 336): the fully symmetric
+ * degree-2p triangle rule with N_Q / (p+1) points times the (p+1)-point Gauss-Legendre rule in
+ * zeta. The geometry is linear in the triangle and in zeta: vertex v = t + 3h of geom[e][6][3]
+ * sits at triangle vertex t = (0,0), (1,0), (0,1) and zeta = -1 (h = 0) or +1 (h = 1).
+ * Algorithm 2 of section 2 per element, eq. (sum_int) of section 5.1, as fem_integrate:
+ *   nel >= 0, p = 1..7 (uniform), geom [nel][6][3] FP64, coeffs as for fem_integrate in the modes
+ *   ELEMENT, FIELD and ELASTIC (coeffs->degree, a_off, b_off, workspace are ignored; coeffs->jac
+ *   must be NULL: FEM_EINVAL otherwise), out_A [nel][Ns][Ns] (ELASTIC [nel][3][3][Ns][Ns]),
+ *   out_b [nel][Ns] (ELASTIC [nel][3][Ns]) or NULL.
+ * Asynchronous on `stream`; allocates nothing. */
+int fem_integrate_prism(int64_t nel, int p, const double *geom, const fem_coeffs *coeffs,
+                        void *out_A, void *out_b, void *stream);
+
+/* HOST copies of the prism's reference data (section 2, Tables 1-2): tri[ntq][3] = (xi1, xi2,
+ * weight) of the triangle rule (ntq = N_Q / (p+1); weights sum to 1/2) and B[Nq][4][Ns] =
+ * (phi_i, d phi_i/d xi1, d phi_i/d xi2, d phi_i/d zeta) at point q = qt + ntq qz. Either pointer
+ * may be NULL. Needs no fem_init and no GPU. FEM_EDEGREE for p outside 1..7. */
+int fem_prism_reference_tables(int p, double *tri, double *B);
+
 /* For callers that cannot allocate device memory (code under stream capture, tight serving
  * loops, harnesses that forbid hipMalloc): fem_integrate with the same arguments, layouts and
  * results, except that a mixed-degree call (p == 0) ignores coeffs->workspace and
@@ -241,13 +265,18 @@ int fem_reference_tables(int p, double *gauss_x, double *gauss_w, double *lobatt
  * default) issues one launch per degree, each with the variant chosen for that degree. */
 #define FEM_MAX_VARIANTS 6
 
-/* Number of variants compiled for (p, precision), p = 0..7 (>= 1), FEM_EDEGREE or FEM_EINVAL
- * (the work-assignment parameters of section 4.2 as compiled alternatives). */
+/* Variant keys of the prism of degree p (p = 1..7) in the calls below. */
+#define FEM_PRISM(p) (10 + (p))
+
+/* Number of variants compiled for (p, precision), p = 0..7 or FEM_PRISM(1..7) (>= 1),
+ * FEM_EDEGREE or FEM_EINVAL (the work-assignment parameters of section 4.2 as compiled
+ * alternatives). */
 int fem_variant_count(int p, int precision);
 
-/* The variant fem_integrate launches for (p, precision, mode) (section 4.2: parameters chosen
- * per degree), or FEM_EDEGREE / FEM_EINVAL. mode is a fem_coef_mode: the coefficient mode
- * changes the per-point prologue, so each mode has its own choice. */
+/* The variant fem_integrate (fem_integrate_prism for p = FEM_PRISM(1..7)) launches for
+ * (p, precision, mode) (section 4.2: parameters chosen per degree), or FEM_EDEGREE / FEM_EINVAL.
+ * mode is a fem_coef_mode: the coefficient mode changes the per-point prologue, so each mode has
+ * its own choice. */
 int fem_get_variant(int p, int precision, int mode);
 
 /* Choose the variant for (p, precision, mode) (section 4.2); FEM_ECONFIG if variant >=
@@ -264,7 +293,8 @@ int fem_mixed_variant(int p, int precision);
  * instead): time every variant on a seeded synthetic batch of nel elements in coefficient mode
  * `mode` (mildly distorted cubes; ELEMENT: CDR records, FIELD: rotations, loads and a seeded
  * field descriptor, ELASTIC: E, nu and body forces; for p = 0 degrees 1..7 drawn with weights
- * 8 - p, the timed call including the device bucketing; ELASTIC needs p >= 1; 1 warm-up and 5
+ * 8 - p, the timed call including the device bucketing; for p = FEM_PRISM(1..7) mildly
+ * distorted prisms through fem_integrate_prism; ELASTIC needs p >= 1; 1 warm-up and 5
  * timed calls each, on a stream of its own), choose the fastest for (p, precision, mode), and,
  * if json_path is not NULL, record the choice and the times in that HOST file, keyed by
  * (architecture, p, precision, mode) (other entries of an existing file are kept). chosen

@@ -31,7 +31,7 @@ HIP_SOURCES = [
     "fem_k_split_bf16.hip",
     "fem_k_split_f16.hip",
 ]
-CXX_SOURCES = ["fem_tables.cpp"]
+CXX_SOURCES = ["fem_tables.cpp", "fem_prism_tables.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]

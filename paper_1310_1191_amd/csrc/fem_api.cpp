@@ -21,6 +21,7 @@
 #include "fem_mixed.h"
 
 static_assert(FEM_NOALLOC_MAX_NEL == fem::NOALLOC_MAX_NEL, "one element capacity of the static scratch");
+static_assert(FEM_PRISM(1) == fem::PRISM_BASE + 1, "one numbering of the prism's variant keys");
 
 namespace fem {
 hipError_t prepare_f64();
@@ -55,6 +56,7 @@ using namespace fem;
 struct DegreeDev {
     const double *xq = nullptr, *wq = nullptr, *LD64 = nullptr;
     const float *LD32 = nullptr;
+    const double *phi64 = nullptr;  // prisms: shape-function values at the points
     const void *row[5][2] = {};
     const void *bcol[3] = {};  // column-operand factor table B per family (FP32, FP32, FP64)
     float c_bound = 0.0f;
@@ -63,7 +65,7 @@ struct DegreeDev {
 struct State {
     int device = -1;
     void *blob = nullptr;  // one device allocation holding every table
-    DegreeDev deg[8];
+    DegreeDev deg[18];     // [p]: hexahedra, [PRISM_BASE + p]: prisms
 };
 // Device address of the static mixed-degree scratch on each device fem_init has run on (taken
 // with that device current; every device holds its own copy of the array).
@@ -115,7 +117,7 @@ double row_value(const std::vector<double> &B, int p, int fam, int g, int rb, in
     const int q = slot_point(fam, g, lane, v);
     const int r = slot_comp(v);
     const int i = rb * fam_tm(fam) + lane % fam_tm(fam);
-    if (q >= ns || i >= ns) return 0.0;
+    if (q >= nq_of(p) || i >= ns) return 0.0;
     return B[(size_t(q) * 4 + r) * ns + i];
 }
 
@@ -130,14 +132,95 @@ struct HostBlob {
     }
 };
 
+struct Offs {
+    size_t xq = 0, wq = 0, ld64 = 0, ld32 = 0, phi64 = 0, row[5][2] = {}, bcol[3] = {};
+    bool has_lo[5] = {}, has_1d = false, has_phi = false;
+    float c_bound = 0.0f;
+};
+
+// The operand tables of element P (hexahedron p or prism PRISM_BASE + p) from its FP64 reference
+// operand B[(q, r)][i]: the column-operand B factors per family and the row operand B^T per
+// precision, in the fragment layouts of fem_layout.h.
+void put_operand_tables(HostBlob &hb, Offs &o, int P, const std::vector<double> &B)
+{
+    const int ns = ns_of(P), nq = nq_of(P);
+    // B in the column-operand fragment layout of each family: [group][table block][lane][slot]
+    // holds B[(q, s)][j] for the lane's column j; one table block per 32 (16) columns of an
+    // element, or a single block whose lanes cycle through an element's columns at the packed
+    // pitch when several elements share a block
+    for (int fam = 0; fam < 3; ++fam) {
+        const int tm = fam_tm(fam), nrb = rblocks_of(P, fam);
+        const bool packed = packed_columns(P, fam);
+        const int tb = packed ? 1 : nrb, ng = groups_padded(P, fam), sl = fam_slots(fam);
+        const size_t count = size_t(ng) * tb * 64 * sl;
+        std::vector<double> v(count, 0.0);
+        for (int g = 0; g < ng; ++g)
+            for (int b = 0; b < tb; ++b)
+                for (int l = 0; l < 64; ++l)
+                    for (int sv = 0; sv < sl; ++sv) {
+                        const int q = slot_point(fam, g, l, sv), r = slot_comp(sv);
+                        const int j = packed ? (l % tm) % packed_pitch(P) : b * tm + l % tm;
+                        if (q < nq && j < ns)
+                            v[((size_t(g) * tb + b) * 64 + l) * sl + sv] = B[(size_t(q) * 4 + r) * ns + j];
+                    }
+        if (fam == MF_F64) {
+            o.bcol[fam] = hb.put(v.data(), count * 8);
+        } else {
+            std::vector<float> f(v.begin(), v.end());
+            o.bcol[fam] = hb.put(f.data(), count * 4);
+        }
+    }
+    for (int prec = 0; prec < 5; ++prec) {
+        const int fam = family_of(prec);
+        const int ng = groups_padded(P, fam), nrb = rblocks_of(P, fam), sl = fam_slots(fam);
+        const size_t count = size_t(ng) * nrb * 64 * sl;
+        o.has_lo[prec] = false;
+        if (prec == PREC_F64) {
+            std::vector<double> v(count);
+            for (int g = 0; g < ng; ++g)
+                for (int rb = 0; rb < nrb; ++rb)
+                    for (int l = 0; l < 64; ++l)
+                        for (int k = 0; k < sl; ++k)
+                            v[((size_t(g) * nrb + rb) * 64 + l) * sl + k] = row_value(B, P, fam, g, rb, l, k);
+            o.row[prec][0] = hb.put(v.data(), count * 8);
+        } else if (prec == PREC_F32) {
+            std::vector<float> v(count);
+            for (int g = 0; g < ng; ++g)
+                for (int rb = 0; rb < nrb; ++rb)
+                    for (int l = 0; l < 64; ++l)
+                        for (int k = 0; k < sl; ++k)
+                            v[((size_t(g) * nrb + rb) * 64 + l) * sl + k] = float(row_value(B, P, fam, g, rb, l, k));
+            o.row[prec][0] = hb.put(v.data(), count * 4);
+        } else {
+            std::vector<uint16_t> hi(count), lo(count);
+            for (int g = 0; g < ng; ++g)
+                for (int rb = 0; rb < nrb; ++rb)
+                    for (int l = 0; l < 64; ++l)
+                        for (int k = 0; k < sl; ++k) {
+                            const size_t idx = ((size_t(g) * nrb + rb) * 64 + l) * sl + k;
+                            const double x = row_value(B, P, fam, g, rb, l, k);
+                            if (prec == PREC_SPLIT_F16) {
+                                const double y = x * double(F16_TABLE_SCALE);
+                                hi[idx] = f16_bits(y);
+                                lo[idx] = f16_bits(y - f16_value(hi[idx]));
+                            } else {
+                                hi[idx] = bf16_bits_rne(float(x));
+                                lo[idx] = bf16_bits_rne(float(x - bf16_value(hi[idx])));
+                            }
+                        }
+            o.row[prec][0] = hb.put(hi.data(), count * 2);
+            if (prec != PREC_BF16) {
+                o.row[prec][1] = hb.put(lo.data(), count * 2);
+                o.has_lo[prec] = true;
+            }
+        }
+    }
+}
+
 int build_tables(State &st)
 {
     HostBlob hb;
-    struct Offs {
-        size_t xq, wq, ld64, ld32, row[5][2], bcol[3];
-        bool has_lo[5];
-        float c_bound;
-    } offs[8];
+    Offs offs[18];
     for (int p = 1; p <= 7; ++p) {
         HostDegreeTables t = make_degree_tables(p);
         const int n = t.n;
@@ -151,84 +234,23 @@ int build_tables(State &st)
                 ld32[(q * n + a) * 2 + 1] = float(t.D[q * n + a]);
             }
         Offs &o = offs[p];
+        o.has_1d = true;
         o.xq = hb.put(t.xq.data(), n * 8);
         o.wq = hb.put(t.wq.data(), n * 8);
         o.ld64 = hb.put(ld64.data(), ld64.size() * 8);
         o.ld32 = hb.put(ld32.data(), ld32.size() * 4);
         o.c_bound = float(F16_C_TARGET / t.bmax);
-        const std::vector<double> B = reference_operand(t);
-        // B in the column-operand fragment layout of each family: [group][table block][lane][slot]
-        // holds B[(q, s)][j] for the lane's column j; one table block per 32 (16) columns of an
-        // element, or a single block whose lanes cycle through the Ns columns when several
-        // elements share a block (p = 1)
-        for (int fam = 0; fam < 3; ++fam) {
-            const int tm = fam_tm(fam), ns = ns_of(p), nrb = rblocks_of(p, fam);
-            const bool packed = 2 * ns <= tm;
-            const int tb = packed ? 1 : nrb, ng = groups_padded(p, fam), sl = fam_slots(fam);
-            const size_t count = size_t(ng) * tb * 64 * sl;
-            std::vector<double> v(count, 0.0);
-            for (int g = 0; g < ng; ++g)
-                for (int b = 0; b < tb; ++b)
-                    for (int l = 0; l < 64; ++l)
-                        for (int sv = 0; sv < sl; ++sv) {
-                            const int q = slot_point(fam, g, l, sv), r = slot_comp(sv);
-                            const int j = packed ? (l % tm) % ns : b * tm + l % tm;
-                            if (q < ns && j < ns)
-                                v[((size_t(g) * tb + b) * 64 + l) * sl + sv] = B[(size_t(q) * 4 + r) * ns + j];
-                        }
-            if (fam == MF_F64) {
-                o.bcol[fam] = hb.put(v.data(), count * 8);
-            } else {
-                std::vector<float> f(v.begin(), v.end());
-                o.bcol[fam] = hb.put(f.data(), count * 4);
-            }
-        }
-        for (int prec = 0; prec < 5; ++prec) {
-            const int fam = family_of(prec);
-            const int ng = groups_padded(p, fam), nrb = rblocks_of(p, fam), sl = fam_slots(fam);
-            const size_t count = size_t(ng) * nrb * 64 * sl;
-            o.has_lo[prec] = false;
-            if (prec == PREC_F64) {
-                std::vector<double> v(count);
-                for (int g = 0; g < ng; ++g)
-                    for (int rb = 0; rb < nrb; ++rb)
-                        for (int l = 0; l < 64; ++l)
-                            for (int s = 0; s < sl; ++s)
-                                v[((size_t(g) * nrb + rb) * 64 + l) * sl + s] = row_value(B, p, fam, g, rb, l, s);
-                o.row[prec][0] = hb.put(v.data(), count * 8);
-            } else if (prec == PREC_F32) {
-                std::vector<float> v(count);
-                for (int g = 0; g < ng; ++g)
-                    for (int rb = 0; rb < nrb; ++rb)
-                        for (int l = 0; l < 64; ++l)
-                            for (int s = 0; s < sl; ++s)
-                                v[((size_t(g) * nrb + rb) * 64 + l) * sl + s] =
-                                    float(row_value(B, p, fam, g, rb, l, s));
-                o.row[prec][0] = hb.put(v.data(), count * 4);
-            } else {
-                std::vector<uint16_t> hi(count), lo(count);
-                for (int g = 0; g < ng; ++g)
-                    for (int rb = 0; rb < nrb; ++rb)
-                        for (int l = 0; l < 64; ++l)
-                            for (int s = 0; s < sl; ++s) {
-                                const size_t idx = ((size_t(g) * nrb + rb) * 64 + l) * sl + s;
-                                const double x = row_value(B, p, fam, g, rb, l, s);
-                                if (prec == PREC_SPLIT_F16) {
-                                    const double y = x * double(F16_TABLE_SCALE);
-                                    hi[idx] = f16_bits(y);
-                                    lo[idx] = f16_bits(y - f16_value(hi[idx]));
-                                } else {
-                                    hi[idx] = bf16_bits_rne(float(x));
-                                    lo[idx] = bf16_bits_rne(float(x - bf16_value(hi[idx])));
-                                }
-                            }
-                o.row[prec][0] = hb.put(hi.data(), count * 2);
-                if (prec != PREC_BF16) {
-                    o.row[prec][1] = hb.put(lo.data(), count * 2);
-                    o.has_lo[prec] = true;
-                }
-            }
-        }
+        put_operand_tables(hb, o, p, reference_operand(t));
+    }
+    for (int p = 1; p <= 7; ++p) {
+        HostPrismTables t;
+        if (!make_prism_tables(p, t)) return FEM_ECONFIG;
+        Offs &o = offs[PRISM_BASE + p];
+        o.xq = hb.put(t.pts.data(), t.pts.size() * 8);  // [Nq][4]: xi1, xi2, zeta, weight
+        o.phi64 = hb.put(t.phi.data(), t.phi.size() * 8);
+        o.has_phi = true;
+        o.c_bound = float(F16_C_TARGET / t.bmax);
+        put_operand_tables(hb, o, PRISM_BASE + p, t.B);
     }
     void *d = nullptr;
     if (hipMalloc(&d, hb.bytes.size()) != hipSuccess) return FEM_ENOMEM;
@@ -238,13 +260,17 @@ int build_tables(State &st)
     }
     st.blob = d;
     unsigned char *base = static_cast<unsigned char *>(d);
-    for (int p = 1; p <= 7; ++p) {
-        const Offs &o = offs[p];
-        DegreeDev &dd = st.deg[p];
+    for (int P = 1; P < 18; ++P) {
+        if (P > 7 && P <= PRISM_BASE) continue;
+        const Offs &o = offs[P];
+        DegreeDev &dd = st.deg[P];
         dd.xq = reinterpret_cast<const double *>(base + o.xq);
-        dd.wq = reinterpret_cast<const double *>(base + o.wq);
-        dd.LD64 = reinterpret_cast<const double *>(base + o.ld64);
-        dd.LD32 = reinterpret_cast<const float *>(base + o.ld32);
+        if (o.has_1d) {
+            dd.wq = reinterpret_cast<const double *>(base + o.wq);
+            dd.LD64 = reinterpret_cast<const double *>(base + o.ld64);
+            dd.LD32 = reinterpret_cast<const float *>(base + o.ld32);
+        }
+        if (o.has_phi) dd.phi64 = reinterpret_cast<const double *>(base + o.phi64);
         dd.c_bound = o.c_bound;
         for (int fam = 0; fam < 3; ++fam) dd.bcol[fam] = base + o.bcol[fam];
         for (int prec = 0; prec < 5; ++prec) {
@@ -292,13 +318,16 @@ hipError_t dispatch_variant(int prec, int p, int v, const KArgs &a, hipStream_t 
 // strategy.
 constexpr int NMODES = 3;
 struct Choices {
-    int v[8][5][NMODES];
+    int v[18][5][NMODES];  // [p] hexahedra (0: mixed strategy), [PRISM_BASE + p] prisms
     Choices()
     {
         for (int prec = 0; prec < 5; ++prec)
             for (int mode = 0; mode < NMODES; ++mode) {
                 v[0][prec][mode] = MIXED_PER_DEGREE;
-                for (int p = 1; p <= 7; ++p) v[p][prec][mode] = default_variant(p, family_of(prec));
+                for (int p = 1; p <= 7; ++p) {
+                    v[p][prec][mode] = default_variant(p, family_of(prec));
+                    v[PRISM_BASE + p][prec][mode] = default_variant(PRISM_BASE + p, family_of(prec));
+                }
             }
     }
 };
@@ -346,6 +375,7 @@ void set_degree(KArgs &a, int p, int prec)
     a.wq = d.wq;
     a.LD64 = d.LD64;
     a.LD32 = d.LD32;
+    a.phi64 = d.phi64;
     a.row_hi = d.row[prec][0];
     a.row_lo = d.row[prec][1];
     a.bcol = d.bcol[family_of(prec)];
@@ -480,6 +510,42 @@ int fem_mixed_offsets(int64_t nel, const int8_t *degree, int64_t *a_off, int64_t
 
 namespace {
 
+// One element kind and degree P (hexahedron p or prism PRISM_BASE + p) over nel elements; the
+// arguments are checked by the caller.
+int integrate_uniform(int64_t nel, int P, const double *geom, const fem_coeffs *coeffs, void *out_A,
+                      void *out_b, hipStream_t s)
+{
+    KArgs a = base_args(coeffs, geom, out_A, out_b);
+    a.nel = nel;
+    set_degree(a, P, coeffs->precision);
+    if (coeffs->mode == FEM_COEF_ELASTIC) {
+        // blocks (test component i, trial component k), one launch each, written with element
+        // strides 9 Ns^2 and 3 Ns; the load vector of component i comes with block (i, i). Where
+        // it pays, the blocks below the diagonal are the transposes of those above (major
+        // symmetry of c_ijkl) and are copied instead of integrated.
+        const int64_t nsq = a.a_stride, ns = a.b_stride;
+        const bool wide = coeffs->precision == FEM_FP64 || coeffs->precision == FEM_FP32;
+        const bool sym = wide ? ELASTIC_SYM_WIDE[deg_of(P)] : ELASTIC_SYM_K16[deg_of(P)];
+        for (int i = 0; i < 3; ++i)
+            for (int k = sym ? i : 0; k < 3; ++k) {
+                KArgs ab = a;
+                ab.comp_i = i;
+                ab.comp_k = k;
+                ab.a_base = (3 * i + k) * nsq;
+                ab.a_stride = 9 * nsq;
+                ab.b_base = i * ns;
+                ab.b_stride = 3 * ns;
+                ab.out_b = (i == k) ? out_b : nullptr;
+                ab.status = (i == 0 && k == 0) ? coeffs->status : nullptr;
+                if (dispatch(coeffs->precision, FEM_COEF_ELASTIC, P, ab, s, g_cus) != hipSuccess) return FEM_EHIP;
+            }
+        if (sym && transpose_elastic_blocks(out_A, coeffs->precision == FEM_FP64, nel, (int)ns, s, g_cus) != hipSuccess)
+            return FEM_EHIP;
+        return FEM_OK;
+    }
+    return dispatch(coeffs->precision, coeffs->mode, P, a, s, g_cus) == hipSuccess ? FEM_OK : FEM_EHIP;
+}
+
 // fem_integrate with the mixed-degree workspace given explicitly (the caller's, or the static
 // scratch of fem_integrate_noalloc).
 int integrate_impl(int64_t nel, int p, const double *geom, const fem_coeffs *coeffs, void *out_A,
@@ -498,39 +564,8 @@ int integrate_impl(int64_t nel, int p, const double *geom, const fem_coeffs *coe
     if (!out_A || !coeffs->elem || (!geom && !coeffs->jac)) return FEM_EINVAL;
     if (coeffs->mode == FEM_COEF_FIELD && (!coeffs->field || !geom)) return FEM_EINVAL;
     const hipStream_t s = (hipStream_t)stream;
+    if (p > 0) return integrate_uniform(nel, p, geom, coeffs, out_A, out_b, s);
     KArgs a = base_args(coeffs, geom, out_A, out_b);
-    if (p > 0 && coeffs->mode == FEM_COEF_ELASTIC) {
-        // blocks (test component i, trial component k), one launch each, written with element
-        // strides 9 Ns^2 and 3 Ns; the load vector of component i comes with block (i, i). Where
-        // it pays, the blocks below the diagonal are the transposes of those above (major
-        // symmetry of c_ijkl) and are copied instead of integrated.
-        a.nel = nel;
-        set_degree(a, p, coeffs->precision);
-        const int64_t nsq = a.a_stride, ns = a.b_stride;
-        const bool wide = coeffs->precision == FEM_FP64 || coeffs->precision == FEM_FP32;
-        const bool sym = wide ? ELASTIC_SYM_WIDE[p] : ELASTIC_SYM_K16[p];
-        for (int i = 0; i < 3; ++i)
-            for (int k = sym ? i : 0; k < 3; ++k) {
-                KArgs ab = a;
-                ab.comp_i = i;
-                ab.comp_k = k;
-                ab.a_base = (3 * i + k) * nsq;
-                ab.a_stride = 9 * nsq;
-                ab.b_base = i * ns;
-                ab.b_stride = 3 * ns;
-                ab.out_b = (i == k) ? out_b : nullptr;
-                ab.status = (i == 0 && k == 0) ? coeffs->status : nullptr;
-                if (dispatch(coeffs->precision, FEM_COEF_ELASTIC, p, ab, s, g_cus) != hipSuccess) return FEM_EHIP;
-            }
-        if (sym && transpose_elastic_blocks(out_A, coeffs->precision == FEM_FP64, nel, (int)ns, s, g_cus) != hipSuccess)
-            return FEM_EHIP;
-        return FEM_OK;
-    }
-    if (p > 0) {
-        a.nel = nel;
-        set_degree(a, p, coeffs->precision);
-        return dispatch(coeffs->precision, coeffs->mode, p, a, s, g_cus) == hipSuccess ? FEM_OK : FEM_EHIP;
-    }
     // mixed degree: bucket on the device, then one launch per degree over its bucket
     if (!coeffs->a_off || ((out_b || coeffs->jac) && !coeffs->b_off)) return FEM_EINVAL;
     if (!workspace || workspace_bytes < mixed_workspace_bytes(nel)) return FEM_EWORKSPACE;
@@ -566,6 +601,43 @@ int fem_integrate(int64_t nel, int p, const double *geom, const fem_coeffs *coef
                           coeffs->workspace_bytes);
 }
 
+int fem_integrate_prism(int64_t nel, int p, const double *geom, const fem_coeffs *coeffs,
+                        void *out_A, void *out_b, void *stream)
+{
+    if (!g_state.blob) return FEM_ENOTINIT;
+    if (nel < 0 || !coeffs) return FEM_EINVAL;
+    if (coeffs->precision < FEM_FP64 || coeffs->precision > FEM_SPLIT_FP16) return FEM_EINVAL;
+    if (coeffs->mode != FEM_COEF_ELEMENT && coeffs->mode != FEM_COEF_FIELD &&
+        coeffs->mode != FEM_COEF_ELASTIC)
+        return FEM_EINVAL;
+    if (p < 1 || p > 7) return FEM_EDEGREE;
+    if (coeffs->jac) return FEM_EINVAL;
+    if (nel == 0) return FEM_OK;
+    if (!out_A || !coeffs->elem || !geom) return FEM_EINVAL;
+    if (coeffs->mode == FEM_COEF_FIELD && !coeffs->field) return FEM_EINVAL;
+    return integrate_uniform(nel, PRISM_BASE + p, geom, coeffs, out_A, out_b, (hipStream_t)stream);
+}
+
+int fem_prism_reference_tables(int p, double *tri, double *B)
+{
+    if (p < 1 || p > 7) return FEM_EDEGREE;
+    if (tri) {
+        std::vector<double> x, y, w;
+        if (!prism_triangle_rule(p, x, y, w)) return FEM_ECONFIG;
+        for (size_t k = 0; k < x.size(); ++k) {
+            tri[3 * k] = x[k];
+            tri[3 * k + 1] = y[k];
+            tri[3 * k + 2] = w[k];
+        }
+    }
+    if (B) {
+        HostPrismTables t;
+        if (!make_prism_tables(p, t)) return FEM_ECONFIG;
+        std::memcpy(B, t.B.data(), t.B.size() * sizeof(double));
+    }
+    return FEM_OK;
+}
+
 int fem_integrate_noalloc(int64_t nel, int p, const double *geom, const fem_coeffs *coeffs,
                           void *out_A, void *out_b, void *stream)
 {
@@ -592,11 +664,12 @@ struct TuneBatch {
     std::vector<double> geom, elem, field;
     int reclen = 14;
 };
-TuneBatch tune_batch(int64_t nel, int mode)
+TuneBatch tune_batch(int64_t nel, int mode, bool prism)
 {
     TuneBatch t;
     t.reclen = mode == FEM_COEF_ELEMENT ? 14 : (mode == FEM_COEF_FIELD ? 10 : 5);
-    t.geom.resize(size_t(nel) * 24);
+    const int nv = prism ? 6 : 8;
+    t.geom.resize(size_t(nel) * nv * 3);
     t.elem.assign(size_t(nel) * t.reclen, 0.0);
     uint64_t x = 0x9e3779b97f4a7c15ull;
     auto uni = [&x]() {  // xorshift64*, uniform in [-1, 1)
@@ -604,9 +677,14 @@ TuneBatch tune_batch(int64_t nel, int mode)
         return double((x * 0x2545f4914f6cdd1dull) >> 11) * 0x1.0p-52 - 1.0;
     };
     for (int64_t e = 0; e < nel; ++e) {
-        for (int v = 0; v < 8; ++v)
-            for (int d = 0; d < 3; ++d)
-                t.geom[e * 24 + v * 3 + d] = double((v >> d) & 1) + 0.1 * uni();
+        for (int v = 0; v < nv; ++v)
+            for (int d = 0; d < 3; ++d) {
+                // hexahedron vertex v = v1 + 2 v2 + 4 v3; prism vertex v = t + 3 h (triangle vertex
+                // t at (0,0), (1,0), (0,1), h the layer)
+                const double ref = prism ? (d < 2 ? double(v % 3 == d + 1) : double(v / 3))
+                                         : double((v >> d) & 1);
+                t.geom[(e * nv + v) * 3 + d] = ref + 0.1 * uni();
+            }
         double *r = &t.elem[e * t.reclen];
         if (mode == FEM_COEF_ELEMENT) {
             r[0] = 1.0 + 0.2 * uni(); r[4] = 1.0 + 0.2 * uni(); r[8] = 1.0 + 0.2 * uni();
@@ -701,27 +779,30 @@ bool write_tuning(const char *path, const std::string &arch, const std::vector<T
     return ok && std::rename(tmp.c_str(), path) == 0;
 }
 
+// Keys of the variant tables: 0 (the mixed-degree strategy), 1..7 (hexahedra), FEM_PRISM(1..7).
+bool valid_degree_key(int p) { return (p >= 0 && p <= 7) || (p > PRISM_BASE && p <= PRISM_BASE + 7); }
+
 }  // namespace
 
 extern "C" {
 
 int fem_variant_count(int p, int precision)
 {
-    if (p < 0 || p > 7) return FEM_EDEGREE;
+    if (!valid_degree_key(p)) return FEM_EDEGREE;
     if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16) return FEM_EINVAL;
     return variant_count(precision, p);
 }
 
 int fem_get_variant(int p, int precision, int mode)
 {
-    if (p < 0 || p > 7) return FEM_EDEGREE;
+    if (!valid_degree_key(p)) return FEM_EDEGREE;
     if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16 || mode < 0 || mode >= NMODES) return FEM_EINVAL;
     return g_choice.v[p][precision][mode];
 }
 
 int fem_set_variant(int p, int precision, int mode, int variant)
 {
-    if (p < 0 || p > 7) return FEM_EDEGREE;
+    if (!valid_degree_key(p)) return FEM_EDEGREE;
     if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16 || mode < 0 || mode >= NMODES) return FEM_EINVAL;
     if (variant < 0 || variant >= variant_count(precision, p)) return FEM_ECONFIG;
     g_choice.v[p][precision][mode] = variant;
@@ -739,14 +820,15 @@ int fem_autotune(int p, int precision, int mode, int64_t nel, const char *json_p
                  double *times_ms)
 {
     if (!g_state.blob) return FEM_ENOTINIT;
-    if (p < 0 || p > 7) return FEM_EDEGREE;
+    if (!valid_degree_key(p)) return FEM_EDEGREE;
     if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16 || nel <= 0 || mode < 0 || mode >= NMODES)
         return FEM_EINVAL;
     if (mode == FEM_COEF_ELASTIC && p == 0) return FEM_EINVAL;
+    const bool prism = is_prism(p);
     const int nv = variant_count(precision, p);
     const size_t osz = precision == FEM_FP64 ? 8 : 4;
     const int64_t blocks = mode == FEM_COEF_ELASTIC ? 9 : 1, comps = mode == FEM_COEF_ELASTIC ? 3 : 1;
-    const TuneBatch tb = tune_batch(nel, mode);
+    const TuneBatch tb = tune_batch(nel, mode, prism);
     // p = 0: degrees 1..7 with weights 8 - p, interleaved; offsets by an exclusive scan
     std::vector<int8_t> deg;
     std::vector<int64_t> a_off(1, 0), b_off(1, 0);
@@ -818,6 +900,8 @@ int fem_autotune(int p, int precision, int mode, int64_t nel, const char *json_p
     // bucketing of a mixed-degree call)
     auto run = [&](int v) -> bool {
         g_choice.v[p][precision][mode] = v;
+        if (prism)
+            return fem_integrate_prism(nel, deg_of(p), static_cast<const double *>(d_geom), &c, d_A, d_b, s) == FEM_OK;
         return fem_integrate(nel, p, static_cast<const double *>(d_geom), &c, d_A, d_b, s) == FEM_OK;
     };
     constexpr int REPS = 5;

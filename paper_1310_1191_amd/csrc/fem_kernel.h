@@ -72,6 +72,7 @@ struct KArgs {
     const double *xq, *wq;   // [n] Gauss points and weights
     const double *LD64;      // [n][n][2]: (L, D)[gauss point][node]
     const float *LD32;       // the same, rounded to FP32
+    const double *phi64;     // prisms: [Nq][Ns] shape-function values at the points (load vector)
     const void *row_hi;      // row-operand fragment table (fem_layout.h)
     const void *row_lo;      // second table of the split paths, else null
     const void *bcol;        // B[(q, s)][j] in the column-operand fragment layout (FP32; FP64 path FP64)
@@ -106,7 +107,13 @@ struct Cfg {
 template <int P, int PREC, class C>
 struct Shape {
     static constexpr int FAM = family_of(PREC);
-    static constexpr int N = P + 1, NS = N * N * N, NQ = NS;
+    // prisms: N counts the vertical (Gauss-Legendre / GLL) points and nodes; the 1-D tables,
+    // the trilinear map and the sum factorisation belong to the hexahedron
+    static constexpr bool PRISM = is_prism(P);
+    static constexpr int N = deg_of(P) + 1, NS = ns_of(P), NQ = nq_of(P);
+    static constexpr int GEO = PRISM ? 18 : 24;  // vertex coordinates per element
+    static_assert(!PRISM || (C::PROD == 1 && C::BT == 1),
+                  "prisms produce the column operand per wave from the B-factor table");
     static constexpr int TM = fam_tm(FAM), KGP = fam_kgp(FAM), PPL = fam_ppl(FAM);
     static constexpr int SLOTS = fam_slots(FAM);
     static constexpr int NG = groups_of(P, FAM);
@@ -116,7 +123,7 @@ struct Shape {
     static constexpr int NCH = NGP / KC;
     static constexpr int NQP = NGP * KGP;
     static constexpr int NRB = rblocks_of(P, FAM);
-    static constexpr int NSP = (2 * NS <= TM) ? NS : NRB * TM;  // column pitch per element
+    static constexpr int NSP = col_pitch(P, FAM);  // column pitch per element
     static constexpr int EG = C::EG;
     static_assert((EG * NSP) % TM == 0, "element group must fill whole column blocks");
     static constexpr int NCB = EG * NSP / TM;
@@ -154,8 +161,10 @@ struct Shape {
     // 1-D tables, each followed by an all-zero copy of itself (padding columns read zeros)
     static constexpr size_t off_ld64 = off_fld + 176 * 8;                 // 2 x N*N*2 double
     static constexpr size_t off_ld32 = off_ld64 + 2 * N * N * 2 * 8;      // 2 x N*N*2 float
-    static constexpr size_t off_qw = off_ld32 + al16(2 * N * N * 2 * 4);  // 2N double
-    static constexpr size_t off_wf = off_qw + al16(2 * N * 8);            // EG*NQP double
+    // hexahedra: 2N double (1-D points, weights); prisms: NQP x (xi1, xi2, zeta, w) double
+    static constexpr size_t QW = PRISM ? 4 * size_t(NQP) : 2 * size_t(N);
+    static constexpr size_t off_qw = off_ld32 + al16(2 * N * N * 2 * 4);
+    static constexpr size_t off_wf = off_qw + al16(QW * 8);               // EG*NQP double
     static constexpr size_t off_misc = off_wf + EG * NQP * 8;             // dmax (u32), flag (i32)
     static constexpr size_t off_pt = off_misc + al16(EG * 8);             // 3 x NQP int
     static constexpr size_t off_row = off_pt + al16(3 * NQP * 4);         // resident row table
@@ -567,11 +576,11 @@ __device__ inline void fetch_elements(const KArgs &a, const int32_t *elist, cons
         double v = 0.0;
         if (el < it.neg) {
             const int64_t e = element_id(elist, it.e0 + el);
-            if (comp < 24) {
-                if constexpr (SUP) v = a.geom ? a.geom[e * 24 + comp] : 0.0;
-                else v = a.geom[e * 24 + comp];
+            if (comp < S::GEO) {
+                if constexpr (SUP) v = a.geom ? a.geom[e * S::GEO + comp] : 0.0;
+                else v = a.geom[e * S::GEO + comp];
             }
-            else if (comp - 24 < reclen) v = a.elem[e * reclen + (comp - 24)];
+            else if (comp >= 24 && comp - 24 < reclen) v = a.elem[e * reclen + (comp - 24)];
         }
         pf[k] = v;
     }
@@ -629,11 +638,13 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
     __syncthreads();
 
     // ---- trilinear form x(xi) = sum_S c_S prod_{d in S} xi_d, c_S = 1/8 sum_v X_v prod s_vd ----
-    for (int t = tid; t < EG * 24; t += NT) {
-        const int el = t / 24, coord = (t % 24) / 8, sub = t % 8;
-        s_tc[t] = trilinear_coeff(s_geo + el * 24, coord, sub);
+    if constexpr (!S::PRISM) {
+        for (int t = tid; t < EG * 24; t += NT) {
+            const int el = t / 24, coord = (t % 24) / 8, sub = t % 8;
+            s_tc[t] = trilinear_coeff(s_geo + el * 24, coord, sub);
+        }
+        __syncthreads();
     }
-    __syncthreads();
 
     // ---- FIELD mode, pass 1: the 7 coefficient fields at x_q, staged in the point's Dh slot ----
     if (a.mode == 1) {
@@ -641,10 +652,13 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
         for (int t = tid; t < EG * NQP; t += NT) {
             const int el = t / NQP, q = t % NQP;
             if (el >= neg || q >= NQ) continue;
-            const int q1 = q % N, q2 = (q / N) % N, q3 = q / (N * N);
-            const double x1 = s_qw[q1], x2 = s_qw[q2], x3 = s_qw[q3];
             double xq[3];
-            trilinear_point(s_tc + el * 24, x1, x2, x3, xq);
+            if constexpr (S::PRISM) {
+                prism_point(s_geo + el * 24, s_qw[4 * q], s_qw[4 * q + 1], s_qw[4 * q + 2], xq);
+            } else {
+                const int q1 = q % N, q2 = (q / N) % N, q3 = q / (N * N);
+                trilinear_point(s_tc + el * 24, s_qw[q1], s_qw[q2], s_qw[q3], xq);
+            }
             double g[7];
             eval_fields(s_fld, xq, g);
             double *stage = reinterpret_cast<double *>(s_D + (size_t)t * S::DSTR);
@@ -665,9 +679,19 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
             s_wf[t] = 0.0;
             continue;
         }
-        const int q1 = q % N, q2 = (q / N) % N, q3 = q / (N * N);
-        const double x1 = s_qw[q1], x2 = s_qw[q2], x3 = s_qw[q3];
-        const double w = s_qw[N + q1] * s_qw[N + q2] * s_qw[N + q3];
+        double x1, x2, x3, w;
+        if constexpr (S::PRISM) {
+            x1 = s_qw[4 * q];
+            x2 = s_qw[4 * q + 1];
+            x3 = s_qw[4 * q + 2];
+            w = s_qw[4 * q + 3];
+        } else {
+            const int q1 = q % N, q2 = (q / N) % N, q3 = q / (N * N);
+            x1 = s_qw[q1];
+            x2 = s_qw[q2];
+            x3 = s_qw[q3];
+            w = s_qw[N + q1] * s_qw[N + q2] * s_qw[N + q3];
+        }
         double Ji[3][3], det;
         if constexpr (SUP) {
             // supplied terms (the NOJAC variant of section 4): detJ, then J^{-1} row-major
@@ -678,6 +702,8 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
             for (int m = 0; m < 3; ++m)
 #pragma unroll
                 for (int n = 0; n < 3; ++n) Ji[m][n] = jt[1 + 3 * m + n];
+        } else if constexpr (S::PRISM) {
+            det = prism_jacobian_terms(s_geo + el * 24, x1, x2, x3, Ji);
         } else {
             det = jacobian_terms(s_tc + el * 24, x1, x2, x3, Ji);
         }
@@ -967,7 +993,7 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
     const int w_q0 = (lane / TM) * S::PPL;
     // PROD 1: point data of k-group g for one element (the PPL points of this lane's half-wave)
     // BT: byte offset of the lane's slots in the B table per column block, and the group stride
-    constexpr bool PACKED = 2 * NS <= TM;  // several elements share a column block (p = 1)
+    constexpr bool PACKED = packed_columns(P, FAM);  // several elements share a column block
     constexpr int TBN = PACKED ? 1 : S::NRB;
     constexpr size_t BGSTRIDE = size_t(TBN) * 64 * S::SLOTS * sizeof(DT);
     int w_bt[C::WN];
@@ -1148,7 +1174,22 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
     // ---- load vector b_i = sum_q w_q detJ_q f phi_i(xi_q), FP64, by one workgroup per element.
     // The sum runs over q1, q2, q3 in turn (phi_i is a product of 1-D factors); same terms, the
     // additions grouped by direction.
-    if (rt == 0 && ct == 0 && a.out_b) {
+    if (S::PRISM && rt == 0 && ct == 0 && a.out_b) {
+        // prisms: b_i = sum_q (w detJ f)_q phi_i(xi_q), the values read from the FP64 table
+        OT *outb = reinterpret_cast<OT *>(a.out_b);
+        for (int t = tid; t < EG * NS; t += NT) {
+            const int el = t / NS, r = t % NS;
+            if (el >= neg) continue;
+            const double *wf = s_wf + (size_t)el * NQP;
+            double sum = 0.0;
+#pragma unroll 4
+            for (int q = 0; q < NQ; ++q) sum += wf[q] * a.phi64[(size_t)q * NS + r];
+            const int64_t e = element_id(elist, e0 + el);
+            const int64_t base = a.b_off ? a.b_off[e] : a.b_base + e * a.b_stride;
+            outb[base + r] = (OT)sum;
+        }
+    }
+    if (!S::PRISM && rt == 0 && ct == 0 && a.out_b) {
         const int tot = EG * NS;
         // t1[el][q3][q2][a] = sum_q1 L[q1][a] wf[el][q1 + N q2 + N^2 q3]
         for (int t = tid; t < tot; t += NT) {
@@ -1373,6 +1414,11 @@ __device__ inline void run_items(const KArgs &a, int64_t wi, const int64_t strid
     int *s_pt = reinterpret_cast<int *>(smem + S::off_pt);
     if (a.mode == 1)
         for (int t = tid; t < 175; t += NT) s_fld[t] = a.field[t];
+    if constexpr (S::PRISM) {
+        // points (xi1, xi2, zeta) and weights; padded points are zero
+        for (int t = tid; t < 4 * S::NQP; t += NT) s_qw[t] = t < 4 * S::NQ ? a.xq[t] : 0.0;
+    }
+    if constexpr (!S::PRISM) {
     for (int t = tid; t < N * N * 2; t += NT) {
         s_ld64[t] = a.LD64[t];
         s_ld32[t] = a.LD32[t];
@@ -1393,6 +1439,7 @@ __device__ inline void run_items(const KArgs &a, int64_t wi, const int64_t strid
             s_pt[2 * S::NQP + q] = ok ? (q / (N * N)) * ROWBYTES : 0;
         }
     }
+    }  // hexahedra
     if constexpr (C::RES == 1) {
         // [frag][part][lane] x 16 B (split), [frag][lane] x 16 B or 32 B otherwise
         typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));

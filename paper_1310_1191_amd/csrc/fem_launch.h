@@ -54,6 +54,25 @@ template <> struct VariantCfg<7, MF_K16, 1> { using type = Cfg<1, 1, 4, 8, 1, 1,
 template <> struct VariantCfg<7, MF_K16, 2> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1>; };
 template <> struct VariantCfg<7, MF_K16, 3> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1, 1>; };
 template <> struct VariantCfg<7, MF_K16, 4> { using type = Cfg<1, 1, 4, 8, 2, 1, 1, 0, 1>; };
+// -- prisms (P = PRISM_BASE + p; Ns = 6, 18, 40, 75, 126, 196, 288): every variant produces the
+// column operand per wave from the B-factor table (PROD 1, BT 1). p = 1 packs 16 elements at a
+// pitch of 8 columns; p = 2, 3, 4 give one element to each wave (1 x 1, 2 x 2, 3 x 3 blocks);
+// p = 5 as the hexahedron of p = 4; p = 6 one element per workgroup in four 7 x 2 wave tiles;
+// p = 7 four tall 9 x 1 wave tiles (three column tiles) or three 9 x 1 waves.
+template <> struct VariantCfg<11, MF_K16, 0> { using type = Cfg<16, 1, 1, 1, 4, 3, 1, 2, 1, 1>; };
+template <> struct VariantCfg<11, MF_K16, 1> { using type = Cfg<16, 1, 4, 1, 1, 3, 1, 2, 1, 1>; };
+template <> struct VariantCfg<12, MF_K16, 0> { using type = Cfg<4, 1, 1, 1, 4, 2, 1, 2, 1, 1>; };
+template <> struct VariantCfg<12, MF_K16, 1> { using type = Cfg<4, 1, 4, 1, 1, 3, 1, 2, 1, 1>; };
+template <> struct VariantCfg<13, MF_K16, 0> { using type = Cfg<4, 1, 4, 2, 2, 2, 1, 2, 1, 1>; };
+template <> struct VariantCfg<13, MF_K16, 1> { using type = Cfg<8, 1, 8, 2, 2, 2, 1, 1, 1, 1>; };
+template <> struct VariantCfg<14, MF_K16, 0> { using type = Cfg<4, 1, 4, 3, 3, 1, 1, 2, 1, 1>; };
+template <> struct VariantCfg<14, MF_K16, 1> { using type = Cfg<4, 1, 4, 3, 3, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<15, MF_K16, 0> { using type = Cfg<4, 1, 4, 4, 4, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<15, MF_K16, 1> { using type = Cfg<1, 1, 4, 4, 1, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<16, MF_K16, 0> { using type = Cfg<1, 1, 4, 7, 2, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<16, MF_K16, 1> { using type = Cfg<1, 1, 4, 7, 1, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<17, MF_K16, 0> { using type = Cfg<1, 1, 4, 9, 1, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<17, MF_K16, 1> { using type = Cfg<1, 1, 3, 9, 1, 1, 1, 0, 1, 1>; };
 template <int P, int V> struct VariantCfg<P, MF_F32, V> { using type = typename VariantCfg<P, MF_K16, V>::type; };
 // -- FP64 (16-wide blocks) --
 template <> struct VariantCfg<1, MF_F64, 0> { using type = Cfg<8, 1, 4, 1, 1, 2, 2, 1, 0>; };
@@ -65,6 +84,15 @@ template <> struct VariantCfg<5, MF_F64, 1> { using type = Cfg<1, 1, 4, 14, 1, 1
 template <> struct VariantCfg<6, MF_F64, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 1, 0, 0>; };
 template <> struct VariantCfg<6, MF_F64, 1> { using type = Cfg<1, 1, 4, 11, 1, 1, 1, 0, 0>; };
 template <> struct VariantCfg<7, MF_F64, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 1, 0, 0>; };
+// prisms, 16-wide blocks: p = 1 packs 8 elements per wave; p = 2, 3 one element per wave; p >= 4
+// one element per workgroup in tall wave tiles holding every row block
+template <> struct VariantCfg<11, MF_F64, 0> { using type = Cfg<8, 1, 1, 1, 4, 2, 1, 2, 1, 1>; };
+template <> struct VariantCfg<12, MF_F64, 0> { using type = Cfg<4, 1, 4, 2, 2, 2, 1, 2, 1, 1>; };
+template <> struct VariantCfg<13, MF_F64, 0> { using type = Cfg<4, 1, 4, 3, 3, 1, 1, 2, 1, 1>; };
+template <> struct VariantCfg<14, MF_F64, 0> { using type = Cfg<1, 1, 4, 5, 1, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<15, MF_F64, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<16, MF_F64, 0> { using type = Cfg<1, 1, 4, 13, 1, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<17, MF_F64, 0> { using type = Cfg<1, 1, 4, 18, 1, 1, 1, 0, 1, 1>; };
 
 template <int P, int PREC, int V>
 struct Inst {
@@ -88,7 +116,8 @@ struct Inst {
     static hipError_t prepare()
     {
         const hipError_t e = prepare_one<false>();
-        return e != hipSuccess ? e : prepare_one<true>();
+        if constexpr (is_prism(P)) return e;  // prisms take no supplied Jacobian terms
+        else return e != hipSuccess ? e : prepare_one<true>();
     }
     // a.nel is the exact element count, or an upper bound when a.seg supplies the count. The
     // grid is persistent: at most the workgroups the device holds at once.
@@ -104,7 +133,8 @@ struct Inst {
     }
     static hipError_t launch(const KArgs &a, hipStream_t s, int cus)
     {
-        return a.jac ? launch_one<true>(a, s, cus) : launch_one<false>(a, s, cus);
+        if constexpr (is_prism(P)) return a.jac ? hipErrorInvalidValue : launch_one<false>(a, s, cus);
+        else return a.jac ? launch_one<true>(a, s, cus) : launch_one<false>(a, s, cus);
     }
 };
 
@@ -153,6 +183,9 @@ hipError_t prepare_all()
     one(prepare_p<1, PREC>()); one(prepare_p<2, PREC>()); one(prepare_p<3, PREC>());
     one(prepare_p<4, PREC>()); one(prepare_p<5, PREC>()); one(prepare_p<6, PREC>());
     one(prepare_p<7, PREC>());
+    one(prepare_p<11, PREC>()); one(prepare_p<12, PREC>()); one(prepare_p<13, PREC>());
+    one(prepare_p<14, PREC>()); one(prepare_p<15, PREC>()); one(prepare_p<16, PREC>());
+    one(prepare_p<17, PREC>());
     return e;
 }
 
@@ -181,6 +214,13 @@ hipError_t launch_p(int p, int v, const KArgs &a, hipStream_t s, int64_t cus)
     case 5: return launch_pv<5, PREC>(v, a, s, (int)cus);
     case 6: return launch_pv<6, PREC>(v, a, s, (int)cus);
     case 7: return launch_pv<7, PREC>(v, a, s, (int)cus);
+    case 11: return launch_pv<11, PREC>(v, a, s, (int)cus);
+    case 12: return launch_pv<12, PREC>(v, a, s, (int)cus);
+    case 13: return launch_pv<13, PREC>(v, a, s, (int)cus);
+    case 14: return launch_pv<14, PREC>(v, a, s, (int)cus);
+    case 15: return launch_pv<15, PREC>(v, a, s, (int)cus);
+    case 16: return launch_pv<16, PREC>(v, a, s, (int)cus);
+    case 17: return launch_pv<17, PREC>(v, a, s, (int)cus);
     default: return hipErrorInvalidValue;
     }
 }
@@ -196,6 +236,13 @@ int variants_p(int p)
     case 5: return count_variants<5, PREC>();
     case 6: return count_variants<6, PREC>();
     case 7: return count_variants<7, PREC>();
+    case 11: return count_variants<11, PREC>();
+    case 12: return count_variants<12, PREC>();
+    case 13: return count_variants<13, PREC>();
+    case 14: return count_variants<14, PREC>();
+    case 15: return count_variants<15, PREC>();
+    case 16: return count_variants<16, PREC>();
+    case 17: return count_variants<17, PREC>();
     default: return 0;
     }
 }
@@ -205,6 +252,7 @@ int variants_p(int p)
 // single-launch mixed-degree kernel (256-thread workgroups only).
 constexpr int default_variant(int p, int fam)
 {
+    if (is_prism(p)) return 0;
     constexpr int f64[8] = {0, 0, 0, 0, 0, 1, 1, 0};
     if (fam == MF_F64) return f64[p];
     constexpr int k16[8] = {0, 2, 2, 1, 3, 4, 4, 4};

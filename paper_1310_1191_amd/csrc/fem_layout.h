@@ -38,12 +38,46 @@ FEM_HD constexpr int fam_kgp(int fam) { return fam == MF_F32 ? 2 : 4; }
 FEM_HD constexpr int fam_ppl(int fam) { return fam == MF_K16 ? 2 : 1; }
 FEM_HD constexpr int fam_slots(int fam) { return fam == MF_K16 ? 8 : 4; }
 
-FEM_HD constexpr int ns_of(int p) { return (p + 1) * (p + 1) * (p + 1); }
-FEM_HD constexpr int groups_of(int p, int fam) { return (ns_of(p) + fam_kgp(fam) - 1) / fam_kgp(fam); }
+// Element kinds share the kernels: the degree argument P of the tables and kernel templates is
+// p for the hexahedron of degree p and PRISM_BASE + p for the prism of degree p (the reference
+// element of section 2, Tables 1-2: the complete degree-p polynomials on the triangle times the
+// 1-D degree-p polynomials in the vertical direction).
+constexpr int PRISM_BASE = 10;
+FEM_HD constexpr bool is_prism(int P) { return P > PRISM_BASE; }
+FEM_HD constexpr int deg_of(int P) { return is_prism(P) ? P - PRISM_BASE : P; }
+// Triangle points of the prism's quadrature (Table 1: N_Q / (p+1)).
+FEM_HD constexpr int prism_tri_points(int p)
+{
+    return p == 1 ? 3 : p == 2 ? 6 : p == 3 ? 12 : p == 4 ? 16 : p == 5 ? 25 : p == 6 ? 33 : 42;
+}
+// Shape functions and quadrature points per element: (p+1)^3 and (p+1)^3 for the hexahedron,
+// (p+1)^2 (p+2)/2 and prism_tri_points(p) (p+1) for the prism.
+FEM_HD constexpr int ns_of(int P)
+{
+    return is_prism(P) ? (deg_of(P) + 1) * (deg_of(P) + 1) * (deg_of(P) + 2) / 2
+                       : (P + 1) * (P + 1) * (P + 1);
+}
+FEM_HD constexpr int nq_of(int P)
+{
+    return is_prism(P) ? prism_tri_points(deg_of(P)) * (deg_of(P) + 1) : ns_of(P);
+}
+FEM_HD constexpr int groups_of(int p, int fam) { return (nq_of(p) + fam_kgp(fam) - 1) / fam_kgp(fam); }
 // Row-operand tables hold this many k-groups (a multiple of 8, so that every chunk size of the
 // kernels divides it); groups past groups_of() are zero.
 FEM_HD constexpr int groups_padded(int p, int fam) { return (groups_of(p, fam) + 7) / 8 * 8; }
 FEM_HD constexpr int rblocks_of(int p, int fam) { return (ns_of(p) + fam_tm(fam) - 1) / fam_tm(fam); }
+// Column pitch of an element in the column operand: elements with at most half a block of trial
+// functions share blocks at the smallest power-of-two pitch >= Ns (it divides the block width, so
+// every block holds whole elements); larger elements start at a block boundary.
+FEM_HD constexpr bool packed_columns(int p, int fam) { return 2 * ns_of(p) <= fam_tm(fam); }
+FEM_HD constexpr int packed_pitch(int p)
+{
+    return ns_of(p) <= 1 ? 1 : ns_of(p) <= 2 ? 2 : ns_of(p) <= 4 ? 4 : ns_of(p) <= 8 ? 8 : 16;
+}
+FEM_HD constexpr int col_pitch(int p, int fam)
+{
+    return packed_columns(p, fam) ? packed_pitch(p) : rblocks_of(p, fam) * fam_tm(fam);
+}
 
 // Point and component addressed by (group g, lane l, slot v).
 FEM_HD constexpr int slot_point(int fam, int g, int lane, int v)

@@ -32,4 +32,17 @@ HostDegreeTables make_degree_tables(int p);
 // B[(q, r)][i] in FP64 for the whole reference element, [nq][4][ns].
 std::vector<double> reference_operand(const HostDegreeTables &t);
 
+// The prism of degree p (section 2, Tables 1-2): triangle lattice times GLL nodes, the
+// symmetric degree-2p triangle rule times the (p+1)-point Gauss-Legendre rule.
+struct HostPrismTables {
+    int p = 0, n = 0, nt = 0, ns = 0, ntq = 0, nq = 0;
+    std::vector<double> pts;  // [nq][4]: xi1, xi2, zeta, weight; q = qt + ntq qz
+    std::vector<double> B;    // [nq][4][ns]: value and d/dxi1, d/dxi2, d/dzeta; i = t + nt c
+    std::vector<double> phi;  // [nq][ns]: the values alone (load vector)
+    double bmax = 0.0;        // max over (q, j) of sum_r |B[(q, r)][j]|
+};
+// Points (xi1, xi2) and weights of the degree-2p triangle rule; false if the refinement fails.
+bool prism_triangle_rule(int p, std::vector<double> &x, std::vector<double> &y, std::vector<double> &w);
+bool make_prism_tables(int p, HostPrismTables &t);
+
 }  // namespace fem

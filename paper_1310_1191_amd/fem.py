@@ -83,6 +83,9 @@ def load():
     lib.fem_finalize.argtypes = []
     lib.fem_integrate.argtypes = [ctypes.c_int64, ctypes.c_int, vp, ctypes.POINTER(fem_coeffs), vp,
                                   vp, vp]
+    lib.fem_integrate_prism.argtypes = [ctypes.c_int64, ctypes.c_int, vp,
+                                        ctypes.POINTER(fem_coeffs), vp, vp, vp]
+    lib.fem_prism_reference_tables.argtypes = [ctypes.c_int, vp, vp]
     lib.fem_integrate_noalloc.argtypes = [ctypes.c_int64, ctypes.c_int, vp,
                                           ctypes.POINTER(fem_coeffs), vp, vp, vp]
     lib.fem_workspace_bytes.argtypes = [ctypes.c_int64]
@@ -114,7 +117,8 @@ def exported_symbols():
             "fem_mixed_offsets", "fem_field_advance", "fem_reference_tables", "fem_strerror",
             "fem_abi_version", "fem_variant_count", "fem_get_variant", "fem_set_variant",
             "fem_autotune", "fem_load_tuning", "fem_mixed_variant", "fem_jacobian_terms",
-            "fem_integrate_staged", "fem_integrate_noalloc"]
+            "fem_integrate_staged", "fem_integrate_noalloc", "fem_integrate_prism",
+            "fem_prism_reference_tables"]
 
 
 # ---------------------------------------------------------------------------------------------
@@ -162,6 +166,40 @@ def fem_integrate(nel: int, p: int, geom: int, coeffs: fem_coeffs, out_A: int, o
     """Raw call: integer device addresses, returns the status code."""
     return int(load().fem_integrate(int(nel), int(p), geom, ctypes.byref(coeffs), out_A, out_b,
                                     stream))
+
+
+def fem_integrate_prism(nel: int, p: int, geom: int, coeffs: fem_coeffs, out_A: int,
+                        out_b: int | None, stream: int | None) -> int:
+    """Raw call for prisms: integer device addresses, returns the status code."""
+    return int(load().fem_integrate_prism(int(nel), int(p), geom, ctypes.byref(coeffs), out_A,
+                                          out_b, stream))
+
+
+PRISM_TRI_POINTS = {1: 3, 2: 6, 3: 12, 4: 16, 5: 25, 6: 33, 7: 42}
+
+
+def prism(p: int) -> int:
+    """Variant key of the degree-p prism (FEM_PRISM(p))."""
+    return 10 + int(p)
+
+
+def prism_ns(p: int) -> int:
+    return (p + 1) * (p + 1) * (p + 2) // 2
+
+
+def fem_prism_reference_tables(p: int):
+    """Host copies of the prism's triangle rule [ntq, 3] = (xi1, xi2, w) and B [Nq, 4, Ns]."""
+    import numpy as np
+    if not 1 <= p <= 7:
+        raise FemError(FEM_EDEGREE, "fem_prism_reference_tables")
+    ntq = PRISM_TRI_POINTS[p]
+    tri = np.zeros((ntq, 3))
+    B = np.zeros((ntq * (p + 1), 4, prism_ns(p)))
+    rc = load().fem_prism_reference_tables(int(p), ctypes.c_void_p(tri.ctypes.data),
+                                           ctypes.c_void_p(B.ctypes.data))
+    if rc != FEM_OK:
+        raise FemError(rc, "fem_prism_reference_tables")
+    return tri, B
 
 
 def fem_integrate_noalloc(nel: int, p: int, geom: int, coeffs: fem_coeffs, out_A: int,
@@ -353,6 +391,39 @@ def integrate(geom, elem, p: int, precision="split_fp16", mode: int = ELEMENT, f
     rc = fem_integrate(nel, p, _ptr(geom), c, _ptr(out_A), _ptr(out_b), _stream(stream))
     if rc != FEM_OK:
         raise FemError(rc, "fem_integrate")
+    return out_A, out_b
+
+
+def integrate_prism(geom, elem, p: int, precision="split_fp16", mode: int = ELEMENT, field=None,
+                    out_A=None, out_b=None, status=None, with_b: bool = True, stream=None):
+    """Prisms of uniform degree p (geom [nel, 6, 3]): returns (A [nel, Ns, Ns], b [nel, Ns] or
+    None) on the device; for mode ELASTIC (elem [nel, 5]) A is [nel, 3, 3, Ns, Ns], b [nel, 3, Ns]."""
+    torch = _torch()
+    if not 1 <= p <= 7:
+        raise ValueError(f"degree {p} outside 1..7")
+    fem_init(elem.device.index or 0)
+    nel = elem.shape[0]
+    ns = prism_ns(p)
+    dt = out_dtype(precision)
+    if mode not in RECORD_LENGTH:
+        raise ValueError(f"unknown coefficient mode {mode}")
+    _check(elem, torch.float64, "elem", shape=(nel, RECORD_LENGTH[mode]))
+    _check(geom, torch.float64, "geom", shape=(nel, 6, 3))
+    _check(field, torch.float64, "field", min_numel=175)
+    _check(status, torch.int32, "status", min_numel=2)
+    if mode == FIELD and field is None:
+        raise ValueError("FIELD mode needs the field descriptor")
+    ashape, bshape = ((nel, 3, 3, ns, ns), (nel, 3, ns)) if mode == ELASTIC else ((nel, ns, ns), (nel, ns))
+    if out_A is None:
+        out_A = torch.empty(ashape, dtype=dt, device=elem.device)
+    if out_b is None and with_b:
+        out_b = torch.empty(bshape, dtype=dt, device=elem.device)
+    _check(out_A, dt, "out_A", min_numel=nel * (9 if mode == ELASTIC else 1) * ns * ns)
+    _check(out_b, dt, "out_b", min_numel=nel * (3 if mode == ELASTIC else 1) * ns)
+    c = make_coeffs(precision, mode, elem, field=field, status=status)
+    rc = fem_integrate_prism(nel, p, _ptr(geom), c, _ptr(out_A), _ptr(out_b), _stream(stream))
+    if rc != FEM_OK:
+        raise FemError(rc, "fem_integrate_prism")
     return out_A, out_b
 
 

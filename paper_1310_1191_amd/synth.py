@@ -60,6 +60,22 @@ def element_vertices(nodes: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(out.reshape(nx * ny * nz, 8, 3))
 
 
+def prism_vertices(nodes: np.ndarray) -> np.ndarray:
+    """Split every cell of the node grid into two prisms along the diagonal of its xy face and
+    gather [2 nel][6][3] vertex coordinates (vertex v = t + 3h: triangle vertex t of the layer
+    h = 0 below, h = 1 above). Cell e = i + nx (j + ny k) gives prism 2e with the triangle
+    (n00, n10, n01) and prism 2e + 1 with (n11, n01, n10) (both counter-clockwise seen from +z),
+    nab being the cell's node (i + a, j + b)."""
+    nz, ny, nx = (s - 1 for s in nodes.shape[:3])
+    tri = (((0, 0), (1, 0), (0, 1)), ((1, 1), (0, 1), (1, 0)))
+    out = np.empty((nz, ny, nx, 2, 6, 3))
+    for half in range(2):
+        for h in range(2):
+            for t, (a, b) in enumerate(tri[half]):
+                out[:, :, :, half, t + 3 * h, :] = nodes[h:h + nz, b:b + ny, a:a + nx, :]
+    return np.ascontiguousarray(out.reshape(2 * nx * ny * nz, 6, 3))
+
+
 def random_rotations(nel: int, rng: np.random.Generator) -> np.ndarray:
     g = rng.standard_normal((nel, 3, 3))
     q, r = np.linalg.qr(g)
@@ -296,6 +312,33 @@ def _fix_inverted(nodes, nx, ny, nz, alpha, seed, max_iter=200, tol=0.05):
         nodes = nodes.copy()
         nodes[mark] = base[mark] + jit[mark]
     raise RuntimeError("mesh repair did not converge")
+
+
+# Prism workloads (the paper's reference element, section 2): jittered grids of cells split into
+# two prisms each; per prism the CDR coefficient law of the hexahedral workloads ("prism-cdr",
+# seed 6), the elastostatics model problem of section 5.1 ("prism-elastic", seed 7; the paper's
+# own benchmark) or FIELD records ("prism-field", seed 8). Draw order: jitter, then records.
+PRISM_GRIDS = {1: (64, 64, 64), 2: (64, 64, 32), 3: (64, 32, 32), 4: (32, 32, 32),
+               5: (32, 32, 16), 6: (32, 16, 16), 7: (16, 16, 16)}
+PRISM_KINDS = {"cdr": 6, "elastic": 7, "field": 8}
+
+
+def make_prism(kind: str, p: int, grid: tuple | None = None, alpha: float = 0.15) -> Workload:
+    """Prism workload ``kind`` ("cdr", "elastic" or "field") of degree p on ``grid`` cells
+    (default PRISM_GRIDS[p]; 2 nx ny nz prisms)."""
+    seed = PRISM_KINDS[kind]
+    g = tuple(grid) if grid is not None else PRISM_GRIDS[p]
+    nx, ny, nz = g
+    rng = np.random.default_rng(seed)
+    geom = prism_vertices(node_grid(nx, ny, nz, alpha, rng))
+    nel = geom.shape[0]
+    if kind == "cdr":
+        return Workload(f"prism-cdr-p{p}", seed, g, alpha, geom, ELEMENT, cdr_element_coeffs(nel, rng), p=p)
+    if kind == "elastic":
+        return Workload(f"prism-elastic-p{p}", seed, g, alpha, geom, 2, elastic_coeffs(nel, rng), p=p)
+    rec = field_element_records(nel, rng)
+    return Workload(f"prism-field-p{p}", seed, g, alpha, geom, FIELD, rec, p=p,
+                    field=field_descriptor(rng))
 
 
 def small(cfg: int, p: int | None = None, scale: int = 8) -> Workload:

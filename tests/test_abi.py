@@ -119,6 +119,14 @@ def test_variant_table_host_calls(lib):
             assert fem.fem_get_variant(p, prec, fem.ELASTIC) == v0[fem.ELASTIC]
             fem.fem_set_variant(p, prec, fem.FIELD, v0[fem.FIELD])
             assert lib.fem_set_variant(p, prec, fem.ELEMENT, n) == fem.FEM_ECONFIG
+    for p in range(1, 8):  # prisms: keys FEM_PRISM(p) = 10 + p
+        for prec in range(5):
+            n = fem.fem_variant_count(fem.prism(p), prec)
+            assert 1 <= n <= fem.MAX_VARIANTS
+            assert 0 <= fem.fem_get_variant(fem.prism(p), prec, fem.ELEMENT) < n
+    assert lib.fem_variant_count(8, 0) == fem.FEM_EDEGREE
+    assert lib.fem_variant_count(10, 0) == fem.FEM_EDEGREE
+    assert lib.fem_variant_count(18, 0) == fem.FEM_EDEGREE
     for prec in range(5):  # p = 0: the mixed-degree strategies
         assert fem.fem_variant_count(0, prec) == 2
         for m in fem.MODES:
@@ -137,7 +145,7 @@ def test_variant_numbering_is_contiguous():
     fem_variant_count names a compiled kernel."""
     src = open(os.path.join(ROOT, "paper_1310_1191_amd", "csrc", "fem_launch.h")).read()
     seen = {}
-    for p, fam, v in re.findall(r"VariantCfg<(\d), (MF_\w+), (\d)>", src):
+    for p, fam, v in re.findall(r"VariantCfg<(\d+), (MF_\w+), (\d)>", src):
         seen.setdefault((p, fam), []).append(int(v))
     assert seen
     for key, vs in seen.items():
