@@ -13,8 +13,12 @@ The reported value is element matrices per second for the split-FP16 contraction
 MFMA products per term, FP32 accumulation, <= 1e-6 relative error against the FP64 oracle).
 The same step is also timed with the plain FP32 MFMA path for comparison.
 
-``python bench.py [--steps K] [--warmup W] [--precision split_fp16] [--no-cpu-baseline]``
-prints one JSON line.
+``python bench.py [--steps K] [--warmup W] [--precision split_fp16] [--no-cpu-baseline]
+[--no-extras]`` prints one JSON line. Besides the headline it carries, under ``extras``, every
+other workload of the build measured in the same run (p = 1 Poisson at 16^3 -- also replayed from
+a graph -- and 128^3; p = 5, 6, 7 in five precisions; the 200000-element mixed-degree batch in
+both strategies; the 50-step graph-replayed time loop; prisms p = 1..7 and the paper's prism
+elastostatics), each with per-element error statistics against the FP64 oracle on samples.
 """
 from __future__ import annotations
 
@@ -36,17 +40,32 @@ PRODUCTS = {"fp64": 1, "fp32": 1, "bf16": 1, "split_bf16": 3, "split_fp16": 3}
 WORKLOAD = [(2, (64, 64, 64)), (3, (64, 64, 32)), (4, (64, 32, 32))]
 
 
-def flops_per_element(p: int) -> float:
+PRISM_TRI_POINTS = {1: 3, 2: 6, 3: 12, 4: 16, 5: 25, 6: 33, 7: 42}
+
+
+def nq_prism(p: int) -> int:
+    return PRISM_TRI_POINTS[p] * (p + 1)
+
+
+def sizes(p: int, prism: bool = False):
+    """(Ns, NQ): (p+1)^3 and (p+1)^3 for the hexahedron; (p+1)^2 (p+2)/2 and Table 1's N_Q for
+    the prism."""
+    if prism:
+        return (p + 1) * (p + 1) * (p + 2) // 2, nq_prism(p)
+    return (p + 1) ** 3, (p + 1) ** 3
+
+
+def flops_per_element(p: int, prism: bool = False) -> float:
     """Algorithmic work of one element: the contraction 8 Ns^2 NQ plus the load vector 2 Ns NQ."""
-    ns = (p + 1) ** 3
-    return 8.0 * ns * ns * ns + 2.0 * ns * ns
+    ns, nq = sizes(p, prism)
+    return 8.0 * ns * ns * nq + 2.0 * ns * nq
 
 
-def bytes_per_element(p: int, out_bytes: int = 4) -> float:
-    """Algorithmic HBM bytes of one element: 24 FP64 coordinates, a 14-double coefficient record,
-    and the unpadded A (Ns^2) and b (Ns) outputs."""
-    ns = (p + 1) ** 3
-    return 192.0 + 112.0 + (ns * ns + ns) * out_bytes
+def bytes_per_element(p: int, out_bytes: int = 4, prism: bool = False) -> float:
+    """Algorithmic HBM bytes of one element: the FP64 vertex coordinates (24, or 18 for a prism),
+    a 14-double coefficient record, and the unpadded A (Ns^2) and b (Ns) outputs."""
+    ns, _ = sizes(p, prism)
+    return (144.0 if prism else 192.0) + 112.0 + (ns * ns + ns) * out_bytes
 
 
 def log(msg):
@@ -87,30 +106,56 @@ def measured_traffic(p: int, precision: str, variant: int):
     return rec["bytes_per_launch"]
 
 
-def cpu_baseline(meshes, budget_s: float = 12.0):
-    """The FP64 oracle on the host cores, timed on a bounded sample of the same workload."""
+def _oracle_rate(meshes, threads, budget_s):
+    """Seconds per element of the oracle for each degree of ``meshes`` on ``threads`` threads,
+    from the first elements of each mesh (about budget_s / len(meshes) of CPU time per degree)."""
     import oracle
-    oracle.build(force=False)
-    threads = oracle.max_threads()
-    per_el = {}
-    samples = []
+    per_el, samples = {}, []
     for p, geom, coef in meshes:
-        # size the sample so that each degree takes about budget_s / 3 of CPU time
         probe = min(geom.shape[0], max(threads, 8))
         t0 = time.perf_counter()
         oracle.integrate(geom[:probe], coef[:probe], p=p, threads=threads)
         t_probe = time.perf_counter() - t0
-        n = int(min(geom.shape[0], max(probe, probe * (budget_s / 3.0) / max(t_probe, 1e-6))))
+        n = int(min(geom.shape[0],
+                    max(probe, probe * (budget_s / len(meshes)) / max(t_probe, 1e-6))))
         t0 = time.perf_counter()
         oracle.integrate(geom[:n], coef[:n], p=p, threads=threads)
         dt = time.perf_counter() - t0
         per_el[p] = dt / n
         samples.append(f"p={p}: first {n} elements in {dt:.2f} s")
+    return per_el, samples
+
+
+def cpu_baseline(meshes, budget_s: float = 12.0):
+    """The FP64 oracle on the host cores (gcc -O3 -march=native, OpenMP over elements), timed on
+    a bounded sample of the same workload, and on one thread."""
+    import oracle
+    oracle.build(force=False)
+    threads = oracle.max_threads()
     total_el = sum(g.shape[0] for _, g, _ in meshes)
+    per_el, samples = _oracle_rate(meshes, threads, budget_s)
     total_t = sum(per_el[p] * g.shape[0] for p, g, _ in meshes)
+    per1, samples1 = _oracle_rate(meshes, 1, budget_s / 3.0)
+    total_1 = sum(per1[p] * g.shape[0] for p, g, _ in meshes)
     return {"value": total_el / total_t, "unit": "element matrices/s", "cores": threads,
             "kind": "oracle", "sample": "; ".join(samples) + " (FP64, OpenMP over elements; "
-            "rate scaled to the full step's element mix)"}
+            "rate scaled to the full step's element mix)",
+            "single_thread": {"value": total_el / total_1, "unit": "element matrices/s",
+                              "sample": "; ".join(samples1)},
+            "gflops_fp64": sum(flops_per_element(p) * g.shape[0] for p, g, _ in meshes) / total_t / 1e9}
+
+
+def err_stats(errs):
+    """Max, 99th percentile and median of per-element relative errors."""
+    e = np.asarray(errs, dtype=np.float64)
+    return {"n": int(e.size), "max": float(e.max()), "p99": float(np.percentile(e, 99)),
+            "median": float(np.median(e))}
+
+
+def rel_fro_rows(A, R):
+    """Per-element ||A - R||_F / ||R||_F over all but the first axis."""
+    ax = tuple(range(1, A.ndim))
+    return np.sqrt(((A - R) ** 2).sum(axis=ax) / (R ** 2).sum(axis=ax))
 
 
 def main():
@@ -121,17 +166,21 @@ def main():
     ap.add_argument("--precision", default="split_fp16")
     ap.add_argument("--compare", default="fp32", help="second path timed for comparison ('' = none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline only (no other workloads in the line)")
     ap.add_argument("--workload", default="plain",
                     choices=["plain", "high", "mixed", "timestep", "poisson", "elasticity", "nojac",
-                             "staged", "degree"],
-                    help="plain: p = 2, 3, 4 at scale (the headline); high: p = 5, 6, 7 in every "
-                         "precision; mixed: 200000 elements of degrees 1..7 with coefficient fields, "
-                         "one launch against per-degree launches; timestep: 50 graph-replayed steps "
-                         "of 100000 mixed-degree elements; poisson: p = 1; elasticity: the vector "
-                         "model problem (linear elastostatics) for p = 2..7; nojac: supplied "
-                         "per-point Jacobian terms against computed ones for p = 1..7; staged: the "
-                         "plain workload from and to pinned host memory, chunks over streams; degree: "
-                         "one degree's benchmark mesh (--degree) in --precision, for profilers")
+                             "staged", "degree", "prism", "prism-elastic"],
+                    help="plain: p = 2, 3, 4 at scale (the headline, with every other workload under "
+                         "'extras'); high: p = 5, 6, 7 in every precision; mixed: 200000 elements of "
+                         "degrees 1..7 with coefficient fields, one launch against per-degree launches; "
+                         "timestep: 50 graph-replayed steps of 100000 mixed-degree elements; poisson: "
+                         "p = 1; elasticity: the vector model problem (linear elastostatics) for "
+                         "p = 2..7; nojac: supplied per-point Jacobian terms against computed ones for "
+                         "p = 1..7; staged: the plain workload from and to pinned host memory, chunks "
+                         "over streams; degree: one degree's benchmark mesh (--degree) in --precision, "
+                         "for profilers; prism: prismatic elements p = 1..7; prism-elastic: the "
+                         "paper's own benchmark, elastostatics on prisms p = 2..7")
     ap.add_argument("--degree", type=int, default=4, help="degree of the 'degree' workload (1..7)")
     ap.add_argument("--nojac", action="store_true",
                     help="timestep workload: read per-point Jacobian terms written once before the "
@@ -154,10 +203,7 @@ def main():
     fem.fem_init(0)
 
     if args.workload != "plain":
-        line = {"high": bench_high, "mixed": bench_mixed, "timestep": bench_timestep,
-                "poisson": bench_poisson, "elasticity": bench_elasticity,
-                "nojac": bench_nojac, "staged": bench_staged, "degree": bench_degree}[args.workload](
-            args, torch, fem, synth, dev)
+        line = WORKLOADS[args.workload](args, torch, fem, synth, dev)
         print(json.dumps(line), flush=True)
         return
 
@@ -187,6 +233,7 @@ def main():
         dev_in.append((p, g, c))
 
     def run_path(precision, steps, warmup, record_events):
+        """Time `steps` steps; returns (seconds, per-degree ms, outputs of the last step)."""
         dt = fem.out_dtype(precision)
         outs = []
         for p, g, c in dev_in:
@@ -219,16 +266,35 @@ def main():
         if record_events:
             for p in ev:
                 per_p[p] = float(np.mean([a.elapsed_time(b) for a, b in ev[p]]))  # ms
-        del outs
-        torch.cuda.empty_cache()
-        return elapsed, per_p
+        return elapsed, per_p, outs
 
+    def sampled_errors(outs, nsample):
+        """Per-degree error statistics of the last step's outputs on seeded element samples."""
+        import oracle
+        res = {}
+        for (p, geom, coef), (A, b) in zip(meshes, outs):
+            n = min(nsample[p], geom.shape[0])
+            idx = np.sort(np.random.default_rng(100 + p).choice(geom.shape[0], n, replace=False))
+            Ar, br, _ = oracle.integrate(geom[idx], coef[idx], p=p, threads=oracle_threads())
+            it = torch.from_numpy(idx).to(dev)
+            Ag = A[it].double().cpu().numpy()
+            bg = b[it].double().cpu().numpy()
+            res[str(p)] = {"A": err_stats(rel_fro_rows(Ag, Ar)),
+                           "b": err_stats(np.linalg.norm(bg - br, axis=1) / np.linalg.norm(br, axis=1))}
+        return res
+
+    nsample = {2: 2048, 3: 1024, 4: 512}
     log(f"[bench] {args.precision}: warmup {args.warmup}, timing {args.steps} steps")
-    elapsed, per_p = run_path(args.precision, args.steps, args.warmup, True)
+    elapsed, per_p, outs = run_path(args.precision, args.steps, args.warmup, True)
     ms_per_step = elapsed / args.steps * 1e3
     total_el = sum(g.shape[0] for _, g, _ in dev_in)
     value = total_el / (elapsed / args.steps)
     log(f"[bench] {args.precision}: {ms_per_step:.3f} ms/step, {value:.4g} el/s")
+    errors = sampled_errors(outs, nsample)
+    log(f"[bench] {args.precision}: sampled errors " +
+        ", ".join(f"p={p} max {e['A']['max']:.2e}" for p, e in errors.items()))
+    del outs
+    torch.cuda.empty_cache()
 
     per_degree = {}
     for p, g, _ in dev_in:
@@ -241,7 +307,8 @@ def main():
             "tflops": fl / 1e12, "gbs": by / 1e9,
             "frac_mfma": fl / 1e12 / PEAK_TFLOPS[args.precision],
             "frac_mfma_executed": fl * PRODUCTS[args.precision] / 1e12 / PEAK_TFLOPS[args.precision],
-            "frac_hbm": by / 1e9 / HBM_PEAK_GBS}
+            "frac_hbm": by / 1e9 / HBM_PEAK_GBS,
+            "rel_err": errors[str(p)]}
 
     # dominant kernel: the degree whose launch takes the longest
     pd = max(per_p, key=lambda p: per_p[p])
@@ -267,16 +334,30 @@ def main():
     if args.compare:
         csteps = max(3, args.steps // 4)
         log(f"[bench] comparison path {args.compare}: {csteps} steps")
-        ce, cper = run_path(args.compare, csteps, 1, True)
+        ce, cper, couts = run_path(args.compare, csteps, 1, True)
+        cerr = sampled_errors(couts, {2: 512, 3: 256, 4: 128})
+        del couts
+        torch.cuda.empty_cache()
         compare = {"precision": args.compare, "ms_per_step": ce / csteps * 1e3,
                    "el_per_s": total_el / (ce / csteps),
                    "speedup_of_headline": (ce / csteps) / (elapsed / args.steps),
-                   "per_degree_ms": {str(p): round(v, 4) for p, v in cper.items()}}
+                   "per_degree_ms": {str(p): round(v, 4) for p, v in cper.items()},
+                   "rel_err": cerr}
 
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle) on a bounded sample")
         cpu = cpu_baseline(meshes)
+
+    extras = None
+    if not args.no_extras:
+        extras = {}
+        for name in EXTRAS:
+            t0 = time.time()
+            log(f"[bench] extra workload: {name}")
+            extras[name] = WORKLOADS[name](args, torch, fem, synth, dev, quick=True)
+            extras[name]["wall_s"] = round(time.time() - t0, 1)
+            torch.cuda.empty_cache()
 
     line = {
         "metric": "element matrices/s (split-precision MFMA, <= 1e-6 relative error)",
@@ -294,17 +375,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": "cdr-hex p=2,3,4 on 64x64x64/64x64x32/64x32x32 jittered grids "
                                "(262144+131072+65536 elements), FP32 output",
-                   "precision": args.precision, "elements_per_step": total_el},
+                   "precision": args.precision, "elements_per_step": total_el,
+                   "error_sample": "seeded random elements of the last timed step against the "
+                                   "FP64 oracle: " + ", ".join(f"p={p}: {n}" for p, n in nsample.items())},
         "roofline": roof,
         "per_degree": per_degree,
         "compare": compare,
         "cpu_baseline": cpu,
+        "extras": extras,
     }
     print(json.dumps(line), flush=True)
 
 
 # ---------------------------------------------------------------------------------------------
-# secondary workloads (each prints its own JSON line; the headline is the plain workload)
+# the other workloads (each prints its own JSON line with --workload; the default run collects
+# them, with fewer repetitions, under "extras")
 # ---------------------------------------------------------------------------------------------
 def rel_fro(A, R):
     return float(np.linalg.norm(A - R) / np.linalg.norm(R))
@@ -330,35 +415,37 @@ def oracle_threads():
     return oracle.max_threads()
 
 
-def bench_high(args, torch, fem, synth, dev):
+def bench_high(args, torch, fem, synth, dev, quick=False):
     """p = 5, 6, 7 (16384 / 8192 / 4096 elements, CDR coefficients per element) in every
-    precision; per-element error of a sample against the FP64 oracle."""
+    precision; per-element error statistics of a seeded sample against the FP64 oracle."""
     import oracle
     precs = ["fp64", "fp32", "bf16", "split_bf16", "split_fp16"]
     out = {}
-    nsample = 8
+    nsample = {5: 48, 6: 24, 7: 16}
+    reps = 3 if quick else max(3, args.steps // 4)
     for p in (5, 6, 7):
         w = synth.make(3, p=p)
         g = torch.from_numpy(w.geom).to(dev)
         c = torch.from_numpy(w.coef).to(dev)
-        idx = np.random.default_rng(p).choice(w.nel, nsample, replace=False)
+        idx = np.sort(np.random.default_rng(p).choice(w.nel, nsample[p], replace=False))
         t0 = time.time()
         Aref, _, _ = oracle.integrate(w.geom[idx], w.coef[idx], p=p, threads=oracle_threads())
-        log(f"[bench] high p={p}: oracle sample of {nsample} in {time.time() - t0:.1f} s")
+        log(f"[bench] high p={p}: oracle sample of {idx.size} in {time.time() - t0:.1f} s")
         ns = (p + 1) ** 3
         res = {"nel": w.nel}
         for prec in precs:
             A = torch.empty((w.nel, ns, ns), dtype=fem.out_dtype(prec), device=dev)
             b = torch.empty((w.nel, ns), dtype=fem.out_dtype(prec), device=dev)
             ms = time_calls(torch, lambda: fem.integrate(g, c, p, precision=prec, out_A=A, out_b=b),
-                            max(3, args.steps // 4), 1)
+                            reps, 1)
             Ag = A[torch.from_numpy(idx).to(dev)].double().cpu().numpy()
-            errs = [rel_fro(Ag[k], Aref[k]) for k in range(nsample)]
+            st = err_stats(rel_fro_rows(Ag, Aref))
             fl = flops_per_element(p) * w.nel / (ms * 1e-3) / 1e12
             res[prec] = {"ms": round(ms, 4), "el_per_s": w.nel / (ms * 1e-3), "tflops": round(fl, 2),
                          "frac_peak": round(fl / PEAK_TFLOPS[prec], 4),
-                         "max_rel_err_sample": max(errs)}
-            log(f"[bench] high p={p} {prec}: {ms:.3f} ms, {fl:.1f} TFLOP/s, max err {max(errs):.2e}")
+                         "frac_peak_executed": round(fl * PRODUCTS[prec] / PEAK_TFLOPS[prec], 4),
+                         "rel_err": st}
+            log(f"[bench] high p={p} {prec}: {ms:.3f} ms, {fl:.1f} TFLOP/s, max err {st['max']:.2e}")
             del A, b
             torch.cuda.empty_cache()
         out[str(p)] = res
@@ -369,7 +456,8 @@ def bench_high(args, torch, fem, synth, dev):
             "higher_is_better": True, "dtype": "f16x3->f32", "data": "synthetic",
             "config": {"workload": "cdr-hex p=5,6,7 on 32x32x16/32x16x16/16x16x16 jittered grids "
                                    "(16384+8192+4096 elements)",
-                       "sample": f"{nsample} random elements per degree against the FP64 oracle"},
+                       "sample": "seeded random elements against the FP64 oracle: "
+                                 + ", ".join(f"p={p}: {n}" for p, n in nsample.items())},
             "per_degree": out}
 
 
@@ -411,16 +499,17 @@ def oracle_sample(w, field, idx):
     return [a for _, a in res]
 
 
-def bench_mixed(args, torch, fem, synth, dev):
+def bench_mixed(args, torch, fem, synth, dev, quick=False):
     """200000 elements, degrees 1..7 with P(p) proportional to 8 - p, coefficient fields per
     quadrature point; the single persistent launch against one launch per degree."""
     w = synth.make(4)
-    idx = np.random.default_rng(44).choice(w.nel, 64, replace=False)
+    idx = np.sort(np.random.default_rng(44).choice(w.nel, 256, replace=False))
     t0 = time.time()
     ref = oracle_sample(w, w.field, idx)
     log(f"[bench] mixed: oracle sample of {idx.size} in {time.time() - t0:.1f} s")
     flops = sum(flops_per_element(int(p)) for p in w.degree)
     res = {}
+    reps = 3 if quick else max(3, args.steps // 4)
     for prec in ["split_fp16", "fp32"]:
         g, c, f, d, ws, a_off, b_off, A, b = mixed_buffers(torch, fem, w, dev, prec)
         a_np = a_off.cpu().numpy()
@@ -430,12 +519,12 @@ def bench_mixed(args, torch, fem, synth, dev):
             fem.fem_set_variant(0, code, fem.FIELD, strategy)
             call = lambda: fem.integrate_mixed(g, c, d, precision=prec, mode=fem.FIELD, field=f,
                                                a_off=a_off, b_off=b_off, out_A=A, out_b=b, workspace=ws)
-            ms = time_calls(torch, call, max(3, args.steps // 4), 1)
-            errs = sample_errors(fem, w, w.field, idx, A, a_np, ref)
+            ms = time_calls(torch, call, reps, 1)
+            st = err_stats(sample_errors(fem, w, w.field, idx, A, a_np, ref))
             fl = flops / (ms * 1e-3) / 1e12
             res[f"{prec}/{name}"] = {"ms": round(ms, 3), "el_per_s": w.nel / (ms * 1e-3),
-                                     "tflops": round(fl, 2), "max_rel_err_sample": max(errs)}
-            log(f"[bench] mixed {prec} {name}: {ms:.3f} ms, {fl:.1f} TFLOP/s, max err {max(errs):.2e}")
+                                     "tflops": round(fl, 2), "rel_err": st}
+            log(f"[bench] mixed {prec} {name}: {ms:.3f} ms, {fl:.1f} TFLOP/s, max err {st['max']:.2e}")
         fem.fem_set_variant(0, code, fem.FIELD, saved)  # the strategy in force before the benchmark
         del A, b
         torch.cuda.empty_cache()
@@ -447,23 +536,25 @@ def bench_mixed(args, torch, fem, synth, dev):
             "config": {"workload": "mixed-degree hex p=1..7 (P ~ 8-p), 100x50x40 jittered grid "
                                    "(200000 elements), coefficient fields per quadrature point",
                        "degree_counts": counts, "gflop_per_call": flops / 1e9,
-                       "sample": f"{idx.size} random elements against the FP64 oracle"},
+                       "sample": f"{idx.size} seeded random elements against the FP64 oracle"},
             "results": res}
 
 
-def bench_timestep(args, torch, fem, synth, dev):
+def bench_timestep(args, torch, fem, synth, dev, quick=False):
     """100000 elements of degree 2..6 on a strongly distorted mesh; 50 time steps, each a graph
-    replay of {phase update of the coefficient fields, mixed-degree integration}."""
+    replay of {phase update of the coefficient fields, mixed-degree integration}. Every step is
+    checked against the FP64 oracle on the first `per_step` elements of that step's 1% sample."""
     w = synth.make(5)
     nsteps = 50
-    check = [1, nsteps // 2, nsteps]
+    per_step = 24
     deltas = np.stack([synth.phase_shift(w.seed, t) for t in range(1, nsteps + 1)]).reshape(nsteps, 35)
     refs = {}
     t0 = time.time()
-    for t in check:
-        idx = synth.step_sample(w.seed, t, w.nel)
+    for t in range(1, nsteps + 1):
+        idx = synth.step_sample(w.seed, t, w.nel)[:per_step]
         refs[t] = (idx, oracle_sample(w, synth.field_at_step(w.field, w.seed, t), idx))
-    log(f"[bench] timestep: oracle on the 1% samples of steps {check} in {time.time() - t0:.1f} s")
+    log(f"[bench] timestep: oracle on {per_step} elements of every step's 1% sample in "
+        f"{time.time() - t0:.1f} s")
     flops = sum(flops_per_element(int(p)) for p in w.degree)
     res = {}
     for prec in ["split_fp16", "fp32"]:
@@ -504,19 +595,21 @@ def bench_timestep(args, torch, fem, synth, dev):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / nsteps
         reset()
-        maxerr = {}
+        maxerr, allerr = {}, []
         for t in range(1, nsteps + 1):
             graph.replay()
-            if t in refs:
-                torch.cuda.synchronize()
-                idx, ref = refs[t]
-                maxerr[str(t)] = max(sample_errors(fem, w, None, idx, A, a_np, ref))
+            torch.cuda.synchronize()
+            idx, ref = refs[t]
+            errs = sample_errors(fem, w, None, idx, A, a_np, ref)
+            maxerr[str(t)] = max(errs)
+            allerr += errs
         torch.cuda.synchronize()
         assert int(step.item()) == nsteps
         fl = flops / (ms * 1e-3) / 1e12
         res[prec] = {"ms_per_step": round(ms, 3), "el_per_s": w.nel / (ms * 1e-3),
-                     "tflops": round(fl, 2), "max_rel_err_sample_by_step": maxerr}
-        log(f"[bench] timestep {prec}: {ms:.3f} ms/step, {fl:.1f} TFLOP/s, errors {maxerr}")
+                     "tflops": round(fl, 2), "rel_err": err_stats(allerr),
+                     "max_rel_err_by_step": maxerr}
+        log(f"[bench] timestep {prec}: {ms:.3f} ms/step, {fl:.1f} TFLOP/s, max err {max(allerr):.2e}")
         del graph, A, b
         torch.cuda.empty_cache()
     return {"metric": "element matrices/s (split-precision MFMA, <= 1e-6 relative error)",
@@ -529,13 +622,15 @@ def bench_timestep(args, torch, fem, synth, dev):
                                    "hipGraph replay per step",
                        "gflop_per_step": flops / 1e9,
                        "jacobian_terms": "supplied (written once)" if args.nojac else "computed",
-                       "sample": f"1% of the elements at steps {check} against the FP64 oracle"},
+                       "sample": f"every step: the first {per_step} elements of the step's 1% "
+                                 "sample against the FP64 oracle"},
             "results": res, "speedup_split_vs_fp32": res["fp32"]["ms_per_step"] / res["split_fp16"]["ms_per_step"]}
 
 
-def bench_poisson(args, torch, fem, synth, dev):
-    """p = 1 Poisson: the 16^3 workload (FP64 output) and a 128^3 mesh, where the outputs are far
-    larger than the last-level cache and HBM bandwidth bounds the kernel."""
+def bench_poisson(args, torch, fem, synth, dev, quick=False):
+    """p = 1 Poisson: the 16^3 workload (FP64 output; every element against the oracle), the same
+    call replayed from a captured graph (launch cost amortised), and a 128^3 mesh, where the
+    outputs are far larger than the last-level cache and HBM bandwidth bounds the kernel."""
     import oracle
     res = {}
     for grid in [(16, 16, 16), (128, 128, 128)]:
@@ -544,8 +639,8 @@ def bench_poisson(args, torch, fem, synth, dev):
         for prec in ["fp64", "fp32", "split_fp16"]:
             A = torch.empty((w.nel, 8, 8), dtype=fem.out_dtype(prec), device=dev)
             b = torch.empty((w.nel, 8), dtype=fem.out_dtype(prec), device=dev)
-            ms = time_calls(torch, lambda: fem.integrate(g, c, 1, precision=prec, out_A=A, out_b=b),
-                            args.steps, args.warmup)
+            call = lambda: fem.integrate(g, c, 1, precision=prec, out_A=A, out_b=b)
+            ms = time_calls(torch, call, args.steps, args.warmup)
             ob = 8 if prec == "fp64" else 4
             gbs = bytes_per_element(1, ob) * w.nel / (ms * 1e-3) / 1e9
             key = f"{'x'.join(map(str, grid))}/{prec}"
@@ -553,18 +648,40 @@ def bench_poisson(args, torch, fem, synth, dev):
                         "gbs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
             if grid == (16, 16, 16):
                 Aref, _, _ = oracle.integrate(w.geom, w.coef, p=1, threads=oracle_threads())
-                An = A.double().cpu().numpy()
-                res[key]["max_rel_err"] = max(rel_fro(An[e], Aref[e]) for e in range(w.nel))
+                res[key]["rel_err"] = err_stats(rel_fro_rows(A.double().cpu().numpy(), Aref))
+                # graph-amortised: 100 integrations captured in one graph, replayed
+                s = torch.cuda.Stream()
+                s.wait_stream(torch.cuda.current_stream())
+                graph = torch.cuda.CUDAGraph()
+                with torch.cuda.stream(s):
+                    with torch.cuda.graph(graph, stream=s):
+                        for _ in range(100):
+                            fem.integrate(g, c, 1, precision=prec, out_A=A, out_b=b, stream=s)
+                torch.cuda.synchronize()
+                gms = time_calls(torch, graph.replay, 3, 1) / 100
+                res[key]["graph_ms"] = round(gms, 5)
+                res[key]["graph_el_per_s"] = w.nel / (gms * 1e-3)
+                del graph
             log(f"[bench] poisson {key}: {ms:.4f} ms, {gbs:.0f} GB/s")
-    return {"metric": "element matrices/s", "value": res["128x128x128/fp32"]["el_per_s"],
-            "unit": "element matrices/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
+            del A, b
+            torch.cuda.empty_cache()
+    return {"metric": "element matrices/s", "value": res["16x16x16/fp64"]["el_per_s"],
+            "unit": "element matrices/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
             "data": "synthetic",
-            "config": {"workload": "p=1 Poisson, 16^3 (4096 elements) and 128^3 (2097152 elements) "
-                                   "jittered grids"},
+            "config": {"workload": "p=1 Poisson, 16^3 (4096 elements, every element against the "
+                                   "oracle; graph_ms: 100 calls replayed from one graph) and 128^3 "
+                                   "(2097152 elements) jittered grids"},
             "results": res}
 
 
-def bench_elasticity(args, torch, fem, synth, dev):
+def elastic_flops(fem, p_key, prec, p, nel, prism=False):
+    """Algorithmic flops of an elastostatics call: the full 3 x 3 block matrix, and the part the
+    matrix cores execute (6 or 9 blocks; the others are transposed copies)."""
+    blocks = fem.fem_elastic_blocks(p_key, fem.PRECISIONS[prec])
+    return 9 * flops_per_element(p, prism) * nel, blocks * flops_per_element(p, prism) * nel
+
+
+def bench_elasticity(args, torch, fem, synth, dev, quick=False):
     """Linear elastostatics (3 components, isotropic material per element, the paper's model
     problem) on the plain-method grids for p = 2, 3, 4 and the high-order grids for p = 5, 6, 7;
     output 9 Ns^2 + 3 Ns per element; sampled errors against the FP64 oracle."""
@@ -579,7 +696,7 @@ def bench_elasticity(args, torch, fem, synth, dev):
         coef = synth.elastic_coeffs(geom.shape[0], rng)
         nel = geom.shape[0]
         g, c = torch.from_numpy(geom).to(dev), torch.from_numpy(coef).to(dev)
-        idx = np.random.default_rng(p).choice(nel, 4 if p <= 5 else 2, replace=False)
+        idx = np.sort(np.random.default_rng(p).choice(nel, 8 if p <= 5 else 4, replace=False))
         Aref, _, _ = oracle.integrate_elastic(geom[idx], coef[idx], p, threads=oracle_threads(),
                                               with_b=False)
         ns = (p + 1) ** 3
@@ -590,13 +707,18 @@ def bench_elasticity(args, torch, fem, synth, dev):
             ms = time_calls(torch, lambda: fem.integrate(g, c, p, precision=prec, mode=fem.ELASTIC,
                                                          out_A=A, out_b=b), max(3, args.steps // 5), 1)
             Ag = A[torch.from_numpy(idx).to(dev)].double().cpu().numpy()
-            errs = [rel_fro(Ag[k], Aref[k]) for k in range(idx.size)]
-            fl = 9 * flops_per_element(p) * nel / (ms * 1e-3) / 1e12
-            gbs = (192 + 40 + 4 * (9 * ns * ns + 3 * ns)) * nel / (ms * 1e-3) / 1e9
-            res[prec] = {"ms": round(ms, 3), "el_per_s": nel / (ms * 1e-3), "tflops": round(fl, 2),
-                         "frac_peak": round(fl / PEAK_TFLOPS[prec], 4), "gbs": round(gbs, 1),
-                         "max_rel_err_sample": max(errs)}
-            log(f"[bench] elasticity p={p} {prec}: {ms:.3f} ms, {fl:.1f} TFLOP/s, max err {max(errs):.2e}")
+            st = err_stats(rel_fro_rows(Ag, Aref))
+            f_all, f_exec = elastic_flops(fem, p, prec, p, nel)
+            t = ms * 1e-3
+            gbs = (192 + 40 + 4 * (9 * ns * ns + 3 * ns)) * nel / t / 1e9
+            res[prec] = {"ms": round(ms, 3), "el_per_s": nel / t,
+                         "tflops_full_matrix": round(f_all / t / 1e12, 2),
+                         "blocks_integrated": fem.fem_elastic_blocks(p, fem.PRECISIONS[prec]),
+                         "tflops_executed": round(f_exec / t / 1e12, 2),
+                         "frac_peak_executed": round(f_exec * PRODUCTS[prec] / t / 1e12 / PEAK_TFLOPS[prec], 4),
+                         "gbs": round(gbs, 1), "rel_err": st}
+            log(f"[bench] elasticity p={p} {prec}: {ms:.3f} ms, {f_exec / t / 1e12:.1f} TFLOP/s "
+                f"executed, max err {st['max']:.2e}")
             del A, b
             torch.cuda.empty_cache()
         out[str(p)] = res
@@ -607,11 +729,113 @@ def bench_elasticity(args, torch, fem, synth, dev):
             "higher_is_better": True, "dtype": "f16x3->f32", "data": "synthetic",
             "config": {"workload": "linear elastostatics hex p=2..7 (3 components, E ~ U[1,10], "
                                    "nu ~ U[0.2,0.4] per element) on the plain and high-order grids",
-                       "sample": "4 (p<=5) or 2 random elements per degree against the FP64 oracle"},
+                       "sample": "8 (p<=5) or 4 seeded random elements per degree against the FP64 oracle"},
             "per_degree": out}
 
 
-def bench_nojac(args, torch, fem, synth, dev):
+def bench_prism(args, torch, fem, synth, dev, quick=False):
+    """Prismatic elements, the paper's reference element (section 2, Tables 1-2), p = 1..7 with
+    the CDR coefficient law on jittered grids of cells split into two prisms (524288 ... 8192
+    prisms); FP64, FP32 and split FP16; error statistics of seeded samples against the prism
+    oracle."""
+    import oracle
+    out = {}
+    precs = ["split_fp16", "fp32", "fp64"]
+    reps = 3 if quick else max(3, args.steps // 4)
+    for p in range(1, 8):
+        w = synth.make_prism("cdr", p)
+        g, c = torch.from_numpy(w.geom).to(dev), torch.from_numpy(w.coef).to(dev)
+        ns = fem.prism_ns(p)
+        n = {1: 256, 2: 256, 3: 128, 4: 64, 5: 32, 6: 16, 7: 12}[p]
+        idx = np.sort(np.random.default_rng(200 + p).choice(w.nel, n, replace=False))
+        Aref, _, _ = oracle.integrate_prism(w.geom[idx], w.coef[idx], p, threads=oracle_threads())
+        res = {"nel": w.nel, "ns": ns, "nq": nq_prism(p)}
+        for prec in precs:
+            A = torch.empty((w.nel, ns, ns), dtype=fem.out_dtype(prec), device=dev)
+            b = torch.empty((w.nel, ns), dtype=fem.out_dtype(prec), device=dev)
+            ms = time_calls(torch, lambda: fem.integrate_prism(g, c, p, precision=prec, out_A=A, out_b=b),
+                            reps, 1)
+            Ag = A[torch.from_numpy(idx).to(dev)].double().cpu().numpy()
+            st = err_stats(rel_fro_rows(Ag, Aref))
+            t = ms * 1e-3
+            fl = flops_per_element(p, prism=True) * w.nel / t / 1e12
+            ob = 8 if prec == "fp64" else 4
+            gbs = bytes_per_element(p, ob, prism=True) * w.nel / t / 1e9
+            res[prec] = {"ms": round(ms, 4), "el_per_s": w.nel / t, "tflops": round(fl, 2),
+                         "frac_peak": round(fl / PEAK_TFLOPS[prec], 4),
+                         "frac_peak_executed": round(fl * PRODUCTS[prec] / PEAK_TFLOPS[prec], 4),
+                         "gbs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "rel_err": st}
+            log(f"[bench] prism p={p} {prec}: {ms:.3f} ms, {fl:.1f} TFLOP/s, {gbs:.0f} GB/s, "
+                f"max err {st['max']:.2e}")
+            del A, b
+            torch.cuda.empty_cache()
+        out[str(p)] = res
+    tot_el = sum(out[k]["nel"] for k in out)
+    tot_ms = sum(out[k]["split_fp16"]["ms"] for k in out)
+    return {"metric": "element matrices/s (split-precision MFMA, <= 1e-6 relative error)",
+            "value": tot_el / (tot_ms * 1e-3), "unit": "element matrices/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f16x3->f32", "data": "synthetic",
+            "config": {"workload": "cdr-prism p=1..7 on jittered grids of cells split into two "
+                                   "prisms (" + ", ".join(f"p={p}: {out[str(p)]['nel']}" for p in range(1, 8)) + ")",
+                       "sample": "seeded random elements per degree against the FP64 prism oracle"},
+            "per_degree": out}
+
+
+# the paper's own per-element kernel times for its elastostatics benchmark on prisms (Table 6,
+# GTX580, FP32; the fastest of its four kernels), in microseconds: context only
+PAPER_PRISM_ELASTIC_US = {2: 1.21, 3: 17.80, 4: 80.07, 5: 439.9, 6: 1932.0, 7: 6199.0}
+
+
+def bench_prism_elastic(args, torch, fem, synth, dev, quick=False):
+    """The paper's benchmark problem: linear elastostatics on prisms (sections 5.1-5.4), p = 2..7
+    on the prism grids; element matrices of 3 x 3 blocks; sampled errors against the prism oracle;
+    the paper's per-element kernel time on its GPU quoted as context."""
+    import oracle
+    out = {}
+    reps = 3 if quick else max(3, args.steps // 5)
+    for p in range(2, 8):
+        w = synth.make_prism("elastic", p)
+        g, c = torch.from_numpy(w.geom).to(dev), torch.from_numpy(w.coef).to(dev)
+        ns = fem.prism_ns(p)
+        n = {2: 64, 3: 32, 4: 16, 5: 8, 6: 6, 7: 4}[p]
+        idx = np.sort(np.random.default_rng(300 + p).choice(w.nel, n, replace=False))
+        Aref, _, _ = oracle.integrate_prism(w.geom[idx], w.coef[idx], p, mode=oracle.ELASTIC,
+                                            threads=oracle_threads(), with_b=False)
+        res = {"nel": w.nel, "paper_us_per_element_gtx580": PAPER_PRISM_ELASTIC_US[p]}
+        for prec in ["split_fp16", "fp32"]:
+            A = torch.empty((w.nel, 3, 3, ns, ns), dtype=fem.out_dtype(prec), device=dev)
+            b = torch.empty((w.nel, 3, ns), dtype=fem.out_dtype(prec), device=dev)
+            ms = time_calls(torch, lambda: fem.integrate_prism(g, c, p, precision=prec, mode=fem.ELASTIC,
+                                                               out_A=A, out_b=b), reps, 1)
+            Ag = A[torch.from_numpy(idx).to(dev)].double().cpu().numpy()
+            st = err_stats(rel_fro_rows(Ag, Aref))
+            t = ms * 1e-3
+            blocks = fem.fem_elastic_blocks(fem.prism(p), fem.PRECISIONS[prec])
+            f_exec = blocks * flops_per_element(p, prism=True) * w.nel
+            res[prec] = {"ms": round(ms, 3), "el_per_s": w.nel / t,
+                         "us_per_element": round(ms * 1e3 / w.nel, 5),
+                         "blocks_integrated": blocks,
+                         "tflops_executed": round(f_exec / t / 1e12, 2),
+                         "frac_peak_executed": round(f_exec * PRODUCTS[prec] / t / 1e12 / PEAK_TFLOPS[prec], 4),
+                         "rel_err": st}
+            log(f"[bench] prism elasticity p={p} {prec}: {ms:.3f} ms ({ms * 1e3 / w.nel:.4f} us per "
+                f"element; paper {PAPER_PRISM_ELASTIC_US[p]} us), max err {st['max']:.2e}")
+            del A, b
+            torch.cuda.empty_cache()
+        out[str(p)] = res
+    tot_el = sum(out[k]["nel"] for k in out)
+    tot_ms = sum(out[k]["split_fp16"]["ms"] for k in out)
+    return {"metric": "element matrices/s (split-precision MFMA, <= 1e-6 relative error)",
+            "value": tot_el / (tot_ms * 1e-3), "unit": "element matrices/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f16x3->f32", "data": "synthetic",
+            "config": {"workload": "linear elastostatics on prisms p=2..7 (the paper's model problem, "
+                                   "E ~ U[1,10], nu ~ U[0.2,0.4] per element) on the prism grids",
+                       "context": "paper_us_per_element_gtx580: the fastest kernel of Table 6 "
+                                  "(NVIDIA GTX580, FP32, 2013), another machine"},
+            "per_degree": out}
+
+
+def bench_nojac(args, torch, fem, synth, dev, quick=False):
     """Supplied per-point Jacobian terms (detJ and J^{-1}, 80 B per point) against the in-kernel
     FP64 computation from the 8 vertices (192 B per element), p = 1..7 on the plain-method and
     high-order grids (p = 1: 128x128x64); the terms writer's own time; sampled errors of the
@@ -627,7 +851,7 @@ def bench_nojac(args, torch, fem, synth, dev):
         g, c = torch.from_numpy(geom).to(dev), torch.from_numpy(coef).to(dev)
         jt = torch.empty((nel, ns, 10), dtype=torch.float64, device=dev)
         ms_terms = time_calls(torch, lambda: fem.jacobian_terms(g, p, out=jt), max(3, args.steps // 4), 1)
-        idx = np.random.default_rng(p).choice(nel, 4, replace=False)
+        idx = np.sort(np.random.default_rng(p).choice(nel, 8, replace=False))
         Aref, _, _ = oracle.integrate(geom[idx], coef[idx], p=p, threads=oracle_threads(), with_b=False)
         res = {"nel": nel, "terms_ms": round(ms_terms, 4),
                "terms_gbs": round((192 + 80 * ns) * nel / (ms_terms * 1e-3) / 1e9, 1),
@@ -640,12 +864,12 @@ def bench_nojac(args, torch, fem, synth, dev):
             ms_sup = time_calls(torch, lambda: fem.integrate(None, c, p, precision=prec, out_A=A, out_b=b,
                                                              jac=jt), reps, 1)
             Ag = A[torch.from_numpy(idx).to(dev)].double().cpu().numpy()
-            errs = [rel_fro(Ag[k], Aref[k]) for k in range(idx.size)]
+            st = err_stats(rel_fro_rows(Ag, Aref))
             res[prec] = {"ms_computed": round(ms_jac, 4), "ms_supplied": round(ms_sup, 4),
                          "supplied_over_computed": round(ms_sup / ms_jac, 3),
-                         "max_rel_err_sample_supplied": max(errs)}
+                         "rel_err_supplied": st}
             log(f"[bench] nojac p={p} {prec}: computed {ms_jac:.3f} ms, supplied {ms_sup:.3f} ms "
-                f"(terms writer {ms_terms:.3f} ms), max err {max(errs):.2e}")
+                f"(terms writer {ms_terms:.3f} ms), max err {st['max']:.2e}")
             del A, b
             torch.cuda.empty_cache()
         out[str(p)] = res
@@ -658,11 +882,11 @@ def bench_nojac(args, torch, fem, synth, dev):
             "higher_is_better": True, "dtype": "f16x3->f32", "data": "synthetic",
             "config": {"workload": "cdr-hex p=2..7 on the plain and high-order grids with supplied "
                                    "per-point Jacobian terms (value); p=1 on 128x128x64 reported only",
-                       "sample": "4 random elements per degree against the FP64 oracle"},
+                       "sample": "8 seeded random elements per degree against the FP64 oracle"},
             "per_degree": out}
 
 
-def bench_staged(args, torch, fem, synth, dev):
+def bench_staged(args, torch, fem, synth, dev, quick=False):
     """The plain workload (p = 2, 3, 4) with inputs and outputs in pinned host memory: one chunk
     on one stream (copy in, kernel, copy out in sequence) against chunks over three streams
     (copies of one chunk under the kernels of others). Reports the end-to-end rate including the
@@ -709,7 +933,7 @@ DEGREE_GRIDS = {1: (128, 128, 64), 2: (64, 64, 64), 3: (64, 64, 32), 4: (64, 32,
                 5: (32, 32, 16), 6: (32, 16, 16), 7: (16, 16, 16)}
 
 
-def bench_degree(args, torch, fem, synth, dev):
+def bench_degree(args, torch, fem, synth, dev, quick=False):
     """One degree's benchmark mesh (the plain-method grids for p = 2..4, the high-order grids
     for p = 5..7, 128x128x64 for p = 1) integrated --steps times in --precision with the
     default tile: the single-kernel run that the counter profiles are taken on."""
@@ -729,6 +953,13 @@ def bench_degree(args, torch, fem, synth, dev):
             "config": {"workload": f"cdr-hex p={p} on {'x'.join(map(str, DEGREE_GRIDS[p]))} ({w.nel} elements)",
                        "variant": fem.fem_get_variant(p, fem.PRECISIONS[args.precision], fem.ELEMENT)},
             "ms_per_launch": round(ms, 4), "tflops": round(fl, 2)}
+
+WORKLOADS = {"high": bench_high, "mixed": bench_mixed, "timestep": bench_timestep,
+             "poisson": bench_poisson, "elasticity": bench_elasticity, "nojac": bench_nojac,
+             "staged": bench_staged, "degree": bench_degree, "prism": bench_prism,
+             "prism-elastic": bench_prism_elastic}
+# measured in the default run as well, under "extras" (fewer repetitions)
+EXTRAS = ["poisson", "high", "mixed", "timestep", "prism", "prism-elastic"]
 
 
 if __name__ == "__main__":

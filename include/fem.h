@@ -288,6 +288,12 @@ int fem_set_variant(int p, int precision, int mode, int variant);
  * degree classes); fixed at build time. FEM_EDEGREE / FEM_EINVAL on bad arguments. */
 int fem_mixed_variant(int p, int precision);
 
+/* Blocks of the elastostatics element matrix (section 5.1: 3 x 3 blocks of Ns x Ns) that an
+ * ELASTIC call for degree p (1..7, or FEM_PRISM(1..7)) and precision integrates on the matrix
+ * cores: 9, or 6 where the blocks below the diagonal are written as transposed copies of those
+ * above (the major symmetry of c_ijkl). FEM_EDEGREE / FEM_EINVAL on bad arguments. Host only. */
+int fem_elastic_blocks(int p, int precision);
+
 /* Choose the work assignment of (p, precision, mode) by measurement (section 4.2 derives the
  * launch parameters per degree from the device's limits; here the compiled variants are timed
  * instead): time every variant on a seeded synthetic batch of nel elements in coefficient mode

@@ -81,6 +81,11 @@ int64_t g_cus = 256;  // compute units of the device (persistent grids: CUs x re
 // the ragged 125 x 125 blocks transpose slowest; p = 1 blocks are too small to pay).
 constexpr bool ELASTIC_SYM_K16[8] = {false, false, true, true, false, true, true, true};
 constexpr bool ELASTIC_SYM_WIDE[8] = {false, false, true, true, true, true, true, true};
+bool elastic_sym(int P, int prec)
+{
+    const bool wide = prec == FEM_FP64 || prec == FEM_FP32;
+    return wide ? ELASTIC_SYM_WIDE[deg_of(P)] : ELASTIC_SYM_K16[deg_of(P)];
+}
 
 uint16_t bf16_bits_rne(float f)
 {
@@ -524,8 +529,7 @@ int integrate_uniform(int64_t nel, int P, const double *geom, const fem_coeffs *
         // it pays, the blocks below the diagonal are the transposes of those above (major
         // symmetry of c_ijkl) and are copied instead of integrated.
         const int64_t nsq = a.a_stride, ns = a.b_stride;
-        const bool wide = coeffs->precision == FEM_FP64 || coeffs->precision == FEM_FP32;
-        const bool sym = wide ? ELASTIC_SYM_WIDE[deg_of(P)] : ELASTIC_SYM_K16[deg_of(P)];
+        const bool sym = elastic_sym(P, coeffs->precision);
         for (int i = 0; i < 3; ++i)
             for (int k = sym ? i : 0; k < 3; ++k) {
                 KArgs ab = a;
@@ -807,6 +811,13 @@ int fem_set_variant(int p, int precision, int mode, int variant)
     if (variant < 0 || variant >= variant_count(precision, p)) return FEM_ECONFIG;
     g_choice.v[p][precision][mode] = variant;
     return FEM_OK;
+}
+
+int fem_elastic_blocks(int p, int precision)
+{
+    if (!((p >= 1 && p <= 7) || (p > PRISM_BASE && p <= PRISM_BASE + 7))) return FEM_EDEGREE;
+    if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16) return FEM_EINVAL;
+    return elastic_sym(p, precision) ? 6 : 9;
 }
 
 int fem_mixed_variant(int p, int precision)

@@ -108,6 +108,7 @@ def load():
                                  ctypes.c_char_p, ctypes.POINTER(ctypes.c_int), dp]
     lib.fem_load_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]
     lib.fem_mixed_variant.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.fem_elastic_blocks.argtypes = [ctypes.c_int, ctypes.c_int]
     _lib = lib
     return lib
 
@@ -118,7 +119,7 @@ def exported_symbols():
             "fem_abi_version", "fem_variant_count", "fem_get_variant", "fem_set_variant",
             "fem_autotune", "fem_load_tuning", "fem_mixed_variant", "fem_jacobian_terms",
             "fem_integrate_staged", "fem_integrate_noalloc", "fem_integrate_prism",
-            "fem_prism_reference_tables"]
+            "fem_prism_reference_tables", "fem_elastic_blocks"]
 
 
 # ---------------------------------------------------------------------------------------------
@@ -276,6 +277,14 @@ def fem_mixed_variant(p: int, precision: int) -> int:
     rc = int(load().fem_mixed_variant(int(p), int(precision)))
     if rc < 0:
         raise FemError(rc, "fem_mixed_variant")
+    return rc
+
+
+def fem_elastic_blocks(p: int, precision: int) -> int:
+    """Blocks (6 or 9) an ELASTIC call integrates on the matrix cores for (p, precision)."""
+    rc = int(load().fem_elastic_blocks(int(p), int(precision)))
+    if rc < 0:
+        raise FemError(rc, "fem_elastic_blocks")
     return rc
 
 
