@@ -182,6 +182,8 @@ def main():
                          "for profilers; prism: prismatic elements p = 1..7; prism-elastic: the "
                          "paper's own benchmark, elastostatics on prisms p = 2..7")
     ap.add_argument("--degree", type=int, default=4, help="degree of the 'degree' workload (1..7)")
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="'degree' workload: the tile variant to launch (default: the library's choice)")
     ap.add_argument("--nojac", action="store_true",
                     help="timestep workload: read per-point Jacobian terms written once before the "
                          "time loop instead of computing them in every step")
@@ -942,6 +944,8 @@ def bench_degree(args, torch, fem, synth, dev, quick=False):
         raise SystemExit("--degree must be 1..7")
     w = synth.make(2, p=max(p, 2), grid=DEGREE_GRIDS[p]) if p <= 4 else synth.make(3, p=p)
     g, c = torch.from_numpy(w.geom).to(dev), torch.from_numpy(w.coef).to(dev)
+    if args.variant >= 0:
+        fem.fem_set_variant(p, fem.PRECISIONS[args.precision], fem.ELEMENT, args.variant)
     ns = (p + 1) ** 3
     A = torch.empty((w.nel, ns, ns), dtype=fem.out_dtype(args.precision), device=dev)
     b = torch.empty((w.nel, ns), dtype=fem.out_dtype(args.precision), device=dev)

@@ -94,7 +94,9 @@ struct Cfg {
     static constexpr int KC = KC_;    // k-groups per LDS chunk of the column operand
     static constexpr int RES = RES_;  // row operand: 0 staged through LDS per chunk, 1 the whole
                                       // table resident in LDS, 2 streamed from the table
-                                      // (L2) into registers one k-group ahead
+                                      // (L2) into registers one k-group ahead, 3 the wave's
+                                      // whole share of the table held in registers (loaded
+                                      // once per item, k loop unrolled; small tables only)
     static constexpr int BT = BT_;    // PROD 1 only: 1 reads the B factors of the column operand
                                       // from a precomputed table instead of forming them from the
                                       // 1-D Lagrange tables
@@ -146,7 +148,8 @@ struct Shape {
     // row operand fragment bytes per lane (both parts)
     static constexpr int ROWB = (PREC == PREC_F64) ? 32 : (SPLIT ? 32 : 16);
     static constexpr size_t ROWTAB = C::RES == 1 ? size_t(NGP) * NRB * 64 * ROWB : 0;
-    static_assert(C::RES != 2 || C::PROD == 1, "rows streamed to registers need per-wave production");
+    static_assert(C::RES != 3 || NGP * C::WM * ROWB / 4 <= 64, "register-resident rows: at most 64 VGPRs");
+    static_assert(C::RES < 2 || C::PROD == 1, "rows held in registers need per-wave production");
     // element data prefetched per thread: 24 coordinates and up to 14 coefficients per element
     static constexpr int EREC = 38;
     static constexpr int PFN = (EG * EREC + NT - 1) / NT;
@@ -1128,7 +1131,19 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
         }
     };
 
-    if constexpr (C::RES == 2) {
+    if constexpr (C::RES == 3) {
+        // ---- main loop, rows held in registers: the wave's row fragments of every k-group are
+        // loaded at once (one L2 round trip per item), the k loop is unrolled, no barrier.
+        typename F::row rres[S::NGP][C::WM];
+#pragma unroll
+        for (int g = 0; g < S::NGP; ++g)
+#pragma unroll
+            for (int i = 0; i < C::WM; ++i)
+                rres[g][i] = load_row_off<PREC>(a, (unsigned)(g * S::NRB + rbl[i]), lane);
+        produce_first();
+#pragma unroll
+        for (int g = 0; g < S::NGP; ++g) step_regs(rres[g], g, g + 1 < S::NGP ? g + 1 : -1, [] {});
+    } else if constexpr (C::RES == 2) {
         // ---- main loop, rows streamed: each wave loads its row fragments of k-group g + 1 from
         // the table (L2-resident) while it multiplies k-group g; no workgroup barrier. The last
         // iteration reloads and reproduces k-group NGP - 1, so the loop body has no branch.

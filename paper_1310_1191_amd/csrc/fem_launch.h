@@ -9,7 +9,8 @@ namespace fem {
 constexpr int MAX_VARIANTS = 6;
 
 // Cfg<EG, WGM, WGN, WM, WN, OCC, KC, RES, PROD> (see fem_kernel.h). For the 32-wide families
-// (FP32, BF16, split): p = 1 packs 16 elements of 8 trial functions into 4 column blocks;
+// (FP32, BF16, split): p = 1 packs 16 elements of 8 trial functions into 4 column blocks
+// (variants 4, 5: the two k-groups of row fragments held in registers);
 // p = 2, 3 put 4 (8) and 2 (4) elements side by side; p = 4 gives one element to a workgroup
 // (variant 3: one element to each wave, 4 x 4 blocks in registers); p >= 5 tile one element
 // into row x column tiles (variant 2: 4 x 4 blocks per wave). FP64 uses 16-wide blocks.
@@ -20,6 +21,8 @@ template <> struct VariantCfg<1, MF_K16, 0> { using type = Cfg<16, 1, 4, 1, 1, 2
 template <> struct VariantCfg<1, MF_K16, 1> { using type = Cfg<16, 1, 4, 1, 1, 3, 2, 1, 1>; };
 template <> struct VariantCfg<1, MF_K16, 2> { using type = Cfg<4, 1, 1, 1, 1, 3, 2, 2, 1, 1>; };
 template <> struct VariantCfg<1, MF_K16, 3> { using type = Cfg<8, 1, 1, 1, 2, 3, 2, 2, 1, 1>; };
+template <> struct VariantCfg<1, MF_K16, 4> { using type = Cfg<4, 1, 1, 1, 1, 3, 2, 3, 1, 1>; };
+template <> struct VariantCfg<1, MF_K16, 5> { using type = Cfg<8, 1, 1, 1, 2, 3, 2, 3, 1, 1>; };
 template <> struct VariantCfg<2, MF_K16, 0> { using type = Cfg<4, 1, 4, 1, 1, 3, 2, 1, 1>; };
 template <> struct VariantCfg<2, MF_K16, 1> { using type = Cfg<8, 1, 4, 1, 2, 2, 2, 1, 1>; };
 template <> struct VariantCfg<2, MF_K16, 2> { using type = Cfg<4, 1, 1, 1, 4, 2, 1, 2, 1, 1>; };
@@ -255,8 +258,8 @@ constexpr int default_variant(int p, int fam)
     if (is_prism(p)) return 0;
     constexpr int f64[8] = {0, 0, 0, 0, 0, 1, 1, 0};
     if (fam == MF_F64) return f64[p];
-    constexpr int k16[8] = {0, 2, 2, 1, 3, 4, 4, 4};
-    constexpr int f32[8] = {0, 3, 2, 1, 5, 4, 4, 4};
+    constexpr int k16[8] = {0, 4, 2, 1, 3, 4, 4, 4};
+    constexpr int f32[8] = {0, 5, 2, 1, 5, 4, 4, 4};
     return fam == MF_F32 ? f32[p] : k16[p];
 }
 constexpr int mixed_variant(int p, int fam)
