@@ -204,11 +204,6 @@ def main():
     dev = torch.device("cuda:0")
     fem.fem_init(0)
 
-    if args.workload != "plain":
-        line = WORKLOADS[args.workload](args, torch, fem, synth, dev)
-        print(json.dumps(line), flush=True)
-        return
-
     if args.copy_probe > 0:
         n = args.copy_probe * (1 << 20) // 4
         x = torch.ones(n, dtype=torch.float32, device=dev)
@@ -219,6 +214,11 @@ def main():
         log(f"[bench] copy probe: 3 x (read {n * 4} B + write {n * 4} B)")
         del x, y
         torch.cuda.empty_cache()
+
+    if args.workload != "plain":
+        line = WORKLOADS[args.workload](args, torch, fem, synth, dev)
+        print(json.dumps(line), flush=True)
+        return
 
     t0 = time.time()
     meshes = []

@@ -259,11 +259,18 @@ int fem_reference_tables(int p, double *gauss_x, double *gauss_w, double *lobatt
  * fem_integrate launches the variant chosen for its (p, precision): a default measured on
  * MI355X until one of the calls below chooses another. The choice is process-wide and not
  * thread-safe.
+ * p = 1 has one more variant, FEM_TRILINEAR_VARIANT(precision): not a tile configuration but
+ * a vector-ALU kernel (8 x 8 x 32 per element is too small for the matrix cores; the element's
+ * memory traffic bounds it): eight lanes per element, FP64 Jacobian terms and point matrices,
+ * the sums in the precision's output type (FP64 for FEM_FP64, FP32 otherwise, which is at
+ * least as accurate as the 16-bit products). It takes ELEMENT coefficients only and is the
+ * default there; FIELD and ELASTIC calls use the tile variants.
  * p = 0 addresses the mixed-degree path (fem_integrate with p == 0), which has two variants:
  * 0 integrates every degree in one persistent launch (the work items of all degrees form one
  * index space, heaviest degree first, each degree with a fixed tile configuration); 1 (the
  * default) issues one launch per degree, each with the variant chosen for that degree. */
 #define FEM_MAX_VARIANTS 6
+#define FEM_TRILINEAR_VARIANT(precision) ((precision) == FEM_FP64 ? 1 : 5)
 
 /* Variant keys of the prism of degree p (p = 1..7) in the calls below. */
 #define FEM_PRISM(p) (10 + (p))
@@ -280,7 +287,8 @@ int fem_variant_count(int p, int precision);
 int fem_get_variant(int p, int precision, int mode);
 
 /* Choose the variant for (p, precision, mode) (section 4.2); FEM_ECONFIG if variant >=
- * fem_variant_count. Every variant computes the same result to the precision's tolerance. */
+ * fem_variant_count, or if it is the p = 1 vector-ALU variant and mode is not ELEMENT. Every
+ * variant computes the same result to the precision's tolerance. */
 int fem_set_variant(int p, int precision, int mode, int variant);
 
 /* The variant (tile configuration) that the single-launch mixed-degree kernel uses for degree
@@ -305,7 +313,8 @@ int fem_elastic_blocks(int p, int precision);
  * if json_path is not NULL, record the choice and the times in that HOST file, keyed by
  * (architecture, p, precision, mode) (other entries of an existing file are kept). chosen
  * (HOST, may be NULL) receives the variant, times_ms (HOST [FEM_MAX_VARIANTS], may be NULL)
- * the mean milliseconds per call of each variant. Allocates and frees device memory for the
+ * the mean milliseconds per call of each variant (-1 for a variant that does not take the
+ * mode). Allocates and frees device memory for the
  * batch and synchronises; not for use under stream capture. */
 int fem_autotune(int p, int precision, int mode, int64_t nel, const char *json_path, int *chosen,
                  double *times_ms);

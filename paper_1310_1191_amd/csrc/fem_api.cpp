@@ -330,8 +330,8 @@ struct Choices {
             for (int mode = 0; mode < NMODES; ++mode) {
                 v[0][prec][mode] = MIXED_PER_DEGREE;
                 for (int p = 1; p <= 7; ++p) {
-                    v[p][prec][mode] = default_variant(p, family_of(prec));
-                    v[PRISM_BASE + p][prec][mode] = default_variant(PRISM_BASE + p, family_of(prec));
+                    v[p][prec][mode] = default_variant(p, family_of(prec), mode);
+                    v[PRISM_BASE + p][prec][mode] = default_variant(PRISM_BASE + p, family_of(prec), mode);
                 }
             }
     }
@@ -809,6 +809,7 @@ int fem_set_variant(int p, int precision, int mode, int variant)
     if (!valid_degree_key(p)) return FEM_EDEGREE;
     if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16 || mode < 0 || mode >= NMODES) return FEM_EINVAL;
     if (variant < 0 || variant >= variant_count(precision, p)) return FEM_ECONFIG;
+    if (variant == trilinear_variant(p, family_of(precision)) && mode != FEM_COEF_ELEMENT) return FEM_ECONFIG;
     g_choice.v[p][precision][mode] = variant;
     return FEM_OK;
 }
@@ -916,7 +917,13 @@ int fem_autotune(int p, int precision, int mode, int64_t nel, const char *json_p
         return fem_integrate(nel, p, static_cast<const double *>(d_geom), &c, d_A, d_b, s) == FEM_OK;
     };
     constexpr int REPS = 5;
+    bool any = false;
     for (int v = 0; v < nv && rc == FEM_OK; ++v) {
+        if (v == trilinear_variant(p, family_of(precision)) && mode != FEM_COEF_ELEMENT) {
+            entry.ms[v] = -1.0;  // ELEMENT mode only
+            if (times_ms) times_ms[v] = -1.0;
+            continue;
+        }
         if (!run(v)) { fail(FEM_EHIP); break; }
         (void)hipEventRecord(ev[0], s);
         for (int r = 0; r < REPS; ++r)
@@ -927,7 +934,8 @@ int fem_autotune(int p, int precision, int mode, int64_t nel, const char *json_p
             fail(FEM_EHIP);
         entry.ms[v] = double(ms) / REPS;
         if (times_ms) times_ms[v] = entry.ms[v];
-        if (v == 0 || entry.ms[v] < best_ms) { best_ms = entry.ms[v]; best = v; }
+        if (!any || entry.ms[v] < best_ms) { best_ms = entry.ms[v]; best = v; }
+        any = true;
     }
     g_choice.v[p][precision][mode] = saved;
     if (ev[0]) (void)hipEventDestroy(ev[0]);

@@ -3,6 +3,7 @@
 // (degree, precision) and records the fastest.
 #pragma once
 #include "fem_kernel.h"
+#include "fem_trilinear.h"
 
 namespace fem {
 
@@ -10,19 +11,22 @@ constexpr int MAX_VARIANTS = 6;
 
 // Cfg<EG, WGM, WGN, WM, WN, OCC, KC, RES, PROD> (see fem_kernel.h). For the 32-wide families
 // (FP32, BF16, split): p = 1 packs 16 elements of 8 trial functions into 4 column blocks
-// (variants 4, 5: the two k-groups of row fragments held in registers);
+// (variants 3, 4: the two k-groups of row fragments held in registers; variant 5 the
+// vector-ALU kernel of fem_trilinear.h, ELEMENT mode only);
 // p = 2, 3 put 4 (8) and 2 (4) elements side by side; p = 4 gives one element to a workgroup
 // (variant 3: one element to each wave, 4 x 4 blocks in registers); p >= 5 tile one element
 // into row x column tiles (variant 2: 4 x 4 blocks per wave). FP64 uses 16-wide blocks.
 template <int P, int FAM, int V> struct VariantCfg { using type = void; };
+// The vector-ALU kernel of trilinear hexahedra (fem_trilinear.h; ELEMENT mode only).
+struct TrilinearCfg {};
 
 // -- 32-wide families --
 template <> struct VariantCfg<1, MF_K16, 0> { using type = Cfg<16, 1, 4, 1, 1, 2, 2, 1, 0>; };
 template <> struct VariantCfg<1, MF_K16, 1> { using type = Cfg<16, 1, 4, 1, 1, 3, 2, 1, 1>; };
 template <> struct VariantCfg<1, MF_K16, 2> { using type = Cfg<4, 1, 1, 1, 1, 3, 2, 2, 1, 1>; };
-template <> struct VariantCfg<1, MF_K16, 3> { using type = Cfg<8, 1, 1, 1, 2, 3, 2, 2, 1, 1>; };
-template <> struct VariantCfg<1, MF_K16, 4> { using type = Cfg<4, 1, 1, 1, 1, 3, 2, 3, 1, 1>; };
-template <> struct VariantCfg<1, MF_K16, 5> { using type = Cfg<8, 1, 1, 1, 2, 3, 2, 3, 1, 1>; };
+template <> struct VariantCfg<1, MF_K16, 3> { using type = Cfg<4, 1, 1, 1, 1, 3, 2, 3, 1, 1>; };
+template <> struct VariantCfg<1, MF_K16, 4> { using type = Cfg<8, 1, 1, 1, 2, 3, 2, 3, 1, 1>; };
+template <> struct VariantCfg<1, MF_K16, 5> { using type = TrilinearCfg; };
 template <> struct VariantCfg<2, MF_K16, 0> { using type = Cfg<4, 1, 4, 1, 1, 3, 2, 1, 1>; };
 template <> struct VariantCfg<2, MF_K16, 1> { using type = Cfg<8, 1, 4, 1, 2, 2, 2, 1, 1>; };
 template <> struct VariantCfg<2, MF_K16, 2> { using type = Cfg<4, 1, 1, 1, 4, 2, 1, 2, 1, 1>; };
@@ -79,6 +83,7 @@ template <> struct VariantCfg<17, MF_K16, 1> { using type = Cfg<1, 1, 3, 9, 1, 1
 template <int P, int V> struct VariantCfg<P, MF_F32, V> { using type = typename VariantCfg<P, MF_K16, V>::type; };
 // -- FP64 (16-wide blocks) --
 template <> struct VariantCfg<1, MF_F64, 0> { using type = Cfg<8, 1, 4, 1, 1, 2, 2, 1, 0>; };
+template <> struct VariantCfg<1, MF_F64, 1> { using type = TrilinearCfg; };
 template <> struct VariantCfg<2, MF_F64, 0> { using type = Cfg<2, 1, 4, 2, 1, 2, 2, 0, 0>; };
 template <> struct VariantCfg<3, MF_F64, 0> { using type = Cfg<1, 1, 4, 4, 1, 2, 2, 0, 0>; };
 template <> struct VariantCfg<4, MF_F64, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 1, 0, 0>; };
@@ -146,17 +151,33 @@ template <int P, int PREC, int V>
 constexpr bool has_variant() { return !std::is_void<typename VariantCfg<P, family_of(PREC), V>::type>::value; }
 
 template <int P, int PREC, int V>
+constexpr bool is_trilinear() { return std::is_same<typename VariantCfg<P, family_of(PREC), V>::type, TrilinearCfg>::value; }
+
+// The variant of the vector-ALU kernel of (p, family), or -1 (p = 1 only).
+constexpr int trilinear_variant(int p, int fam) { return p == 1 ? (fam == MF_F64 ? 1 : 5) : -1; }
+static_assert(std::is_same<VariantCfg<1, MF_K16, trilinear_variant(1, MF_K16)>::type, TrilinearCfg>::value &&
+                  std::is_same<VariantCfg<1, MF_F64, trilinear_variant(1, MF_F64)>::type, TrilinearCfg>::value,
+              "trilinear_variant names the vector-ALU kernel");
+
+template <int P, int PREC, int V>
 hipError_t prepare_variant()
 {
-    if constexpr (has_variant<P, PREC, V>()) return Inst<P, PREC, V>::prepare();
+    if constexpr (is_trilinear<P, PREC, V>()) return hipSuccess;
+    else if constexpr (has_variant<P, PREC, V>()) return Inst<P, PREC, V>::prepare();
     else return hipSuccess;
 }
 
 template <int P, int PREC, int V>
 hipError_t launch_variant(const KArgs &a, hipStream_t s, int cus)
 {
-    if constexpr (has_variant<P, PREC, V>()) return Inst<P, PREC, V>::launch(a, s, cus);
-    else return hipErrorInvalidValue;
+    if constexpr (is_trilinear<P, PREC, V>()) {
+        using DT = typename std::conditional<PREC == PREC_F64, double, float>::type;
+        return launch_trilinear<DT>(a, s, cus);
+    } else if constexpr (has_variant<P, PREC, V>()) {
+        return Inst<P, PREC, V>::launch(a, s, cus);
+    } else {
+        return hipErrorInvalidValue;
+    }
 }
 
 template <int P, int PREC>
@@ -253,13 +274,15 @@ int variants_p(int p)
 // Variant launched for each degree before any tuning (the fastest measured on MI355X at the
 // plain-method and high-order workload sizes), and the variant each degree uses inside the
 // single-launch mixed-degree kernel (256-thread workgroups only).
-constexpr int default_variant(int p, int fam)
+// p = 1 in ELEMENT mode (mode 0) runs the vector-ALU kernel.
+constexpr int default_variant(int p, int fam, int mode)
 {
     if (is_prism(p)) return 0;
+    if (p == 1 && mode == 0) return trilinear_variant(p, fam);
     constexpr int f64[8] = {0, 0, 0, 0, 0, 1, 1, 0};
     if (fam == MF_F64) return f64[p];
-    constexpr int k16[8] = {0, 4, 2, 1, 3, 4, 4, 4};
-    constexpr int f32[8] = {0, 5, 2, 1, 5, 4, 4, 4};
+    constexpr int k16[8] = {0, 3, 2, 1, 3, 4, 4, 4};
+    constexpr int f32[8] = {0, 4, 2, 1, 5, 4, 4, 4};
     return fam == MF_F32 ? f32[p] : k16[p];
 }
 constexpr int mixed_variant(int p, int fam)

@@ -237,6 +237,11 @@ def fem_field_advance(field: int, deltas: int, nsteps: int, step: int, stream: i
 MAX_VARIANTS = 6
 
 
+def trilinear_variant(precision: int) -> int:
+    """FEM_TRILINEAR_VARIANT: the p = 1 vector-ALU variant (ELEMENT mode only)."""
+    return 1 if int(precision) == FP64 else 5
+
+
 def fem_variant_count(p: int, precision: int) -> int:
     rc = int(load().fem_variant_count(int(p), int(precision)))
     if rc < 0:

@@ -113,12 +113,20 @@ def test_variant_table_host_calls(lib):
             assert 1 <= n <= fem.MAX_VARIANTS
             v0 = {m: fem.fem_get_variant(p, prec, m) for m in fem.MODES}
             assert all(0 <= v < n for v in v0.values())
-            fem.fem_set_variant(p, prec, fem.FIELD, n - 1)
-            assert fem.fem_get_variant(p, prec, fem.FIELD) == n - 1
+            # p = 1: the last variant is the vector-ALU kernel, ELEMENT mode only (its default)
+            last = n - 2 if p == 1 else n - 1
+            fem.fem_set_variant(p, prec, fem.FIELD, last)
+            assert fem.fem_get_variant(p, prec, fem.FIELD) == last
             assert fem.fem_get_variant(p, prec, fem.ELEMENT) == v0[fem.ELEMENT]
             assert fem.fem_get_variant(p, prec, fem.ELASTIC) == v0[fem.ELASTIC]
             fem.fem_set_variant(p, prec, fem.FIELD, v0[fem.FIELD])
             assert lib.fem_set_variant(p, prec, fem.ELEMENT, n) == fem.FEM_ECONFIG
+            if p == 1:
+                tri = fem.trilinear_variant(prec)
+                assert tri == n - 1 and v0[fem.ELEMENT] == tri
+                assert v0[fem.FIELD] != tri and v0[fem.ELASTIC] != tri
+                assert lib.fem_set_variant(1, prec, fem.FIELD, tri) == fem.FEM_ECONFIG
+                assert lib.fem_set_variant(1, prec, fem.ELASTIC, tri) == fem.FEM_ECONFIG
     for p in range(1, 8):  # prisms: keys FEM_PRISM(p) = 10 + p
         for prec in range(5):
             n = fem.fem_variant_count(fem.prism(p), prec)
