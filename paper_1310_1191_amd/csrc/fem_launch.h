@@ -85,13 +85,20 @@ template <int P, int V> struct VariantCfg<P, MF_F32, V> { using type = typename 
 template <> struct VariantCfg<1, MF_F64, 0> { using type = Cfg<8, 1, 4, 1, 1, 2, 2, 1, 0>; };
 template <> struct VariantCfg<1, MF_F64, 1> { using type = TrilinearCfg; };
 template <> struct VariantCfg<2, MF_F64, 0> { using type = Cfg<2, 1, 4, 2, 1, 2, 2, 0, 0>; };
+template <> struct VariantCfg<2, MF_F64, 1> { using type = Cfg<4, 1, 4, 2, 2, 2, 1, 2, 1, 1>; };
+template <> struct VariantCfg<2, MF_F64, 2> { using type = Cfg<4, 1, 1, 2, 8, 2, 1, 2, 1, 1>; };
 template <> struct VariantCfg<3, MF_F64, 0> { using type = Cfg<1, 1, 4, 4, 1, 2, 2, 0, 0>; };
+template <> struct VariantCfg<3, MF_F64, 1> { using type = Cfg<2, 1, 4, 4, 2, 2, 1, 2, 1, 1>; };
+template <> struct VariantCfg<3, MF_F64, 2> { using type = Cfg<1, 1, 4, 4, 1, 2, 1, 2, 1, 1>; };
 template <> struct VariantCfg<4, MF_F64, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 1, 0, 0>; };
+template <> struct VariantCfg<4, MF_F64, 1> { using type = Cfg<1, 1, 4, 8, 2, 1, 1, 0, 1>; };
+template <> struct VariantCfg<4, MF_F64, 2> { using type = Cfg<1, 1, 4, 8, 2, 1, 1, 0, 1, 1>; };
 template <> struct VariantCfg<5, MF_F64, 0> { using type = Cfg<1, 1, 4, 7, 1, 1, 1, 0, 0>; };
 template <> struct VariantCfg<5, MF_F64, 1> { using type = Cfg<1, 1, 4, 14, 1, 1, 1, 0, 0>; };
 template <> struct VariantCfg<6, MF_F64, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 1, 0, 0>; };
 template <> struct VariantCfg<6, MF_F64, 1> { using type = Cfg<1, 1, 4, 11, 1, 1, 1, 0, 0>; };
 template <> struct VariantCfg<7, MF_F64, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 1, 0, 0>; };
+template <> struct VariantCfg<7, MF_F64, 1> { using type = Cfg<1, 1, 4, 16, 1, 1, 1, 0, 0>; };
 // prisms, 16-wide blocks: p = 1 packs 8 elements per wave; p = 2, 3 one element per wave; p >= 4
 // one element per workgroup in tall wave tiles holding every row block
 template <> struct VariantCfg<11, MF_F64, 0> { using type = Cfg<8, 1, 1, 1, 4, 2, 1, 2, 1, 1>; };
@@ -279,7 +286,7 @@ constexpr int default_variant(int p, int fam, int mode)
 {
     if (is_prism(p)) return 0;
     if (p == 1 && mode == 0) return trilinear_variant(p, fam);
-    constexpr int f64[8] = {0, 0, 0, 0, 0, 1, 1, 0};
+    constexpr int f64[8] = {0, 0, 1, 1, 1, 1, 1, 1};
     if (fam == MF_F64) return f64[p];
     constexpr int k16[8] = {0, 3, 2, 1, 3, 4, 4, 4};
     constexpr int f32[8] = {0, 4, 2, 1, 5, 4, 4, 4};
