@@ -75,16 +75,18 @@ State g_state;
 std::mutex g_mutex;
 
 int64_t g_cus = 256;  // compute units of the device (persistent grids: CUs x resident WGs)
-// Elasticity: whether the lower blocks are copied as transposes of the upper ones (instead of
-// integrated), per degree, for the 16-bit contraction paths and for FP32 / FP64 (measured on
-// MI355X: the copy costs about one integration of a block at p = 4 on the split path, where
-// the ragged 125 x 125 blocks transpose slowest; p = 1 blocks are too small to pay).
-constexpr bool ELASTIC_SYM_K16[8] = {false, false, true, true, false, true, true, true};
-constexpr bool ELASTIC_SYM_WIDE[8] = {false, false, true, true, true, true, true, true};
-bool elastic_sym(int P, int prec)
+// Elasticity: how the blocks below the diagonal (the transposes of those above, by the major
+// symmetry of c_ijkl) are formed, per degree, for the 16-bit contraction paths and for FP32 /
+// FP64: integrated like the others (E_NINE), copied transposed by a separate kernel after the
+// six upper blocks (E_COPY), or written transposed by the epilogue of the upper block's own
+// launch from the tile it stages anyway (E_EPI, no re-read of the block). Measured on MI355X.
+enum ElasticMode { E_NINE = 0, E_COPY = 1, E_EPI = 2 };
+constexpr int ELASTIC_MODE_K16[8] = {E_NINE, E_NINE, E_COPY, E_COPY, E_EPI, E_COPY, E_COPY, E_COPY};
+constexpr int ELASTIC_MODE_WIDE[8] = {E_NINE, E_NINE, E_COPY, E_COPY, E_COPY, E_COPY, E_COPY, E_COPY};
+int elastic_mode(int P, int prec)
 {
     const bool wide = prec == FEM_FP64 || prec == FEM_FP32;
-    return wide ? ELASTIC_SYM_WIDE[deg_of(P)] : ELASTIC_SYM_K16[deg_of(P)];
+    return wide ? ELASTIC_MODE_WIDE[deg_of(P)] : ELASTIC_MODE_K16[deg_of(P)];
 }
 
 uint16_t bf16_bits_rne(float f)
@@ -527,15 +529,21 @@ int integrate_uniform(int64_t nel, int P, const double *geom, const fem_coeffs *
         // blocks (test component i, trial component k), one launch each, written with element
         // strides 9 Ns^2 and 3 Ns; the load vector of component i comes with block (i, i). Where
         // it pays, the blocks below the diagonal are the transposes of those above (major
-        // symmetry of c_ijkl) and are copied instead of integrated.
+        // symmetry of c_ijkl): copied by a separate kernel, or written by the upper block's
+        // epilogue (at_base: the transposed block's offset, always > 0).
         const int64_t nsq = a.a_stride, ns = a.b_stride;
-        const bool sym = elastic_sym(P, coeffs->precision);
+        // E_EPI needs the chosen tile's epilogue to write transposed blocks; otherwise the copy
+        int em = elastic_mode(P, coeffs->precision);
+        if (em == E_EPI && !trans_variant(coeffs->precision, P, g_choice.v[P][coeffs->precision][FEM_COEF_ELASTIC]))
+            em = E_COPY;
+        const bool sym = em != E_NINE;
         for (int i = 0; i < 3; ++i)
             for (int k = sym ? i : 0; k < 3; ++k) {
                 KArgs ab = a;
                 ab.comp_i = i;
                 ab.comp_k = k;
                 ab.a_base = (3 * i + k) * nsq;
+                ab.at_base = (em == E_EPI && k > i) ? (3 * k + i) * nsq : 0;
                 ab.a_stride = 9 * nsq;
                 ab.b_base = i * ns;
                 ab.b_stride = 3 * ns;
@@ -543,7 +551,7 @@ int integrate_uniform(int64_t nel, int P, const double *geom, const fem_coeffs *
                 ab.status = (i == 0 && k == 0) ? coeffs->status : nullptr;
                 if (dispatch(coeffs->precision, FEM_COEF_ELASTIC, P, ab, s, g_cus) != hipSuccess) return FEM_EHIP;
             }
-        if (sym && transpose_elastic_blocks(out_A, coeffs->precision == FEM_FP64, nel, (int)ns, s, g_cus) != hipSuccess)
+        if (em == E_COPY && transpose_elastic_blocks(out_A, coeffs->precision == FEM_FP64, nel, (int)ns, s, g_cus) != hipSuccess)
             return FEM_EHIP;
         return FEM_OK;
     }
@@ -818,7 +826,7 @@ int fem_elastic_blocks(int p, int precision)
 {
     if (!((p >= 1 && p <= 7) || (p > PRISM_BASE && p <= PRISM_BASE + 7))) return FEM_EDEGREE;
     if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16) return FEM_EINVAL;
-    return elastic_sym(p, precision) ? 6 : 9;
+    return elastic_mode(p, precision) != E_NINE ? 6 : 9;
 }
 
 int fem_mixed_variant(int p, int precision)

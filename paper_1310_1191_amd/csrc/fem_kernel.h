@@ -67,6 +67,9 @@ struct KArgs {
     int32_t *status;         // [2] or null
     int32_t mode;            // 0 ELEMENT, 1 FIELD, 2 ELASTIC (block comp_i, comp_k)
     int32_t comp_i, comp_k;  // ELASTIC: test and trial component of this launch's block
+    int64_t at_base;         // ELASTIC, > 0: the block is also written transposed, element e's
+                             // copy at at_base + e a_stride (block (k, i) = block (i, k)^T), by
+                             // the tiles with TRANS_EPI only; 0: no copy
     int64_t a_base, a_stride;  // without a_off: element e's matrix starts at a_base + e a_stride
     int64_t b_base, b_stride;  // without b_off: element e's vector starts at b_base + e b_stride
     const double *xq, *wq;   // [n] Gauss points and weights
@@ -81,7 +84,7 @@ struct KArgs {
 };
 
 template <int EG_, int WGM_, int WGN_, int WM_, int WN_, int OCC_, int KC_, int RES_, int PROD_ = 0,
-          int BT_ = 0>
+          int BT_ = 0, int TE_ = 0>
 struct Cfg {
     static constexpr int PROD = PROD_;  // 0: C chunks produced by the whole workgroup into LDS;
                                         // 1: each wave produces its own C fragments in registers
@@ -100,6 +103,8 @@ struct Cfg {
     static constexpr int BT = BT_;    // PROD 1 only: 1 reads the B factors of the column operand
                                       // from a precomputed table instead of forming them from the
                                       // 1-D Lagrange tables
+    static constexpr int TE = TE_;    // 1: the per-wave staged epilogue can also write the block
+                                      // transposed (elasticity's lower blocks, KArgs::at_base)
     static constexpr int NW = WGM_ * WGN_;
 };
 
@@ -192,6 +197,10 @@ struct Shape {
     static constexpr bool STAGE_OUT = (RT == 1 && CT == 1) && size_t(EG) * IMG * sizeof(OT) <= 65536 &&
                                       !(WAVE_OWNS_EL && C::NW == 1);
     static constexpr bool STAGE_WAVE = !STAGE_OUT && WAVE_OWNS_EL;
+    // Tiles with TE can also write the transposed block (elasticity's lower blocks) from the
+    // per-wave staged rows; with an odd Ns the column reads of the image are free of bank
+    // conflicts. (A separate tile, so the other instances carry none of this code.)
+    static constexpr bool TRANS_EPI = C::TE && STAGE_WAVE && (NS % 2 == 1);
     static constexpr int WIMG = (TM * NS + 2 * VW - 1) / VW * VW;     // one row block
     // Otherwise a workgroup that owns whole elements with one row of waves stages one row block
     // of all its elements at a time.
@@ -1266,6 +1275,17 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
     };
     // offset of an image so that image index x sits at the same position within 16 bytes as dst[x]
     auto img_shift = [](const OT *dst) { return (int)((reinterpret_cast<uintptr_t>(dst) & 15) / sizeof(OT)); };
+    // The transposed copy (elastic blocks, a.at_base > 0; per-wave staging, TRANS_EPI) of staged
+    // rows r0 .. r0 + nrow - 1, img[rl * NS + c]: destination row c receives them as one
+    // contiguous run at column r0.
+    const bool trans = a.at_base > 0;
+    auto copy_out_t = [&](OT *dT, const OT *img, int nrow, int r0, int t, int nth) {
+#pragma unroll 1
+        for (int x = t; x < NS * TM; x += nth) {
+            const int c = x / TM, rl = x % TM;
+            if (rl < nrow) dT[(int64_t)c * NS + r0 + rl] = img[rl * NS + c];
+        }
+    };
     if constexpr (S::STAGE_WAVE) {
         // This wave's element: column blocks cbt0 .. cbt0 + WN - 1 of the tile are its columns.
         const int el = (cbt0 * TM) / S::NSP;
@@ -1297,6 +1317,8 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 // rows r0 .. r0 + nrow - 1 are one contiguous range of the element's matrix
                 copy_out(dst, img, nrow * NS, lane, 64);
+                if constexpr (S::TRANS_EPI)
+                    if (trans) copy_out_t(outA + a.at_base + e * a.a_stride, img, nrow, r0, lane, 64);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

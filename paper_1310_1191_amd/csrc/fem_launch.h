@@ -43,7 +43,7 @@ template <> struct VariantCfg<4, MF_K16, 0> { using type = Cfg<1, 1, 1, 4, 4, 1,
 template <> struct VariantCfg<4, MF_K16, 1> { using type = Cfg<2, 1, 4, 4, 2, 1, 1, 0, 1>; };
 template <> struct VariantCfg<4, MF_K16, 2> { using type = Cfg<2, 1, 4, 4, 2, 2, 1, 0, 1>; };
 template <> struct VariantCfg<4, MF_K16, 3> { using type = Cfg<4, 1, 4, 4, 4, 1, 1, 0, 1>; };
-template <> struct VariantCfg<4, MF_K16, 4> { using type = Cfg<1, 1, 1, 4, 4, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<4, MF_K16, 4> { using type = Cfg<4, 1, 4, 4, 4, 1, 1, 0, 1, 0, 1>; };
 template <> struct VariantCfg<4, MF_K16, 5> { using type = Cfg<2, 1, 4, 4, 2, 2, 1, 0, 1, 1>; };
 template <> struct VariantCfg<5, MF_K16, 0> { using type = Cfg<1, 1, 4, 4, 1, 1, 2, 0, 0>; };
 template <> struct VariantCfg<5, MF_K16, 1> { using type = Cfg<1, 1, 4, 4, 1, 1, 2, 0, 1>; };
@@ -187,6 +187,61 @@ hipError_t launch_variant(const KArgs &a, hipStream_t s, int cus)
     }
 }
 
+// Whether a variant's epilogue can also write the transposed block (a.at_base, elasticity's
+// lower blocks): the per-wave staged epilogue with an odd Ns (Shape::TRANS_EPI).
+template <int P, int PREC, int V>
+constexpr bool trans_epilogue()
+{
+    using Cf = typename VariantCfg<P, family_of(PREC), V>::type;
+    if constexpr (std::is_void<Cf>::value || std::is_same<Cf, TrilinearCfg>::value) return false;
+    else return Shape<P, PREC, Cf>::TRANS_EPI;
+}
+template <int P, int PREC>
+bool trans_pv(int v)
+{
+    switch (v) {
+    case 0: return trans_epilogue<P, PREC, 0>();
+    case 1: return trans_epilogue<P, PREC, 1>();
+    case 2: return trans_epilogue<P, PREC, 2>();
+    case 3: return trans_epilogue<P, PREC, 3>();
+    case 4: return trans_epilogue<P, PREC, 4>();
+    case 5: return trans_epilogue<P, PREC, 5>();
+    default: return false;
+    }
+}
+template <int PREC>
+bool trans_p(int p, int v)
+{
+    switch (p) {
+    case 1: return trans_pv<1, PREC>(v);
+    case 2: return trans_pv<2, PREC>(v);
+    case 3: return trans_pv<3, PREC>(v);
+    case 4: return trans_pv<4, PREC>(v);
+    case 5: return trans_pv<5, PREC>(v);
+    case 6: return trans_pv<6, PREC>(v);
+    case 7: return trans_pv<7, PREC>(v);
+    case 11: return trans_pv<11, PREC>(v);
+    case 12: return trans_pv<12, PREC>(v);
+    case 13: return trans_pv<13, PREC>(v);
+    case 14: return trans_pv<14, PREC>(v);
+    case 15: return trans_pv<15, PREC>(v);
+    case 16: return trans_pv<16, PREC>(v);
+    case 17: return trans_pv<17, PREC>(v);
+    default: return false;
+    }
+}
+inline bool trans_variant(int prec, int p, int v)
+{
+    switch (prec) {
+    case PREC_F64: return trans_p<PREC_F64>(p, v);
+    case PREC_F32: return trans_p<PREC_F32>(p, v);
+    case PREC_BF16: return trans_p<PREC_BF16>(p, v);
+    case PREC_SPLIT_BF16: return trans_p<PREC_SPLIT_BF16>(p, v);
+    case PREC_SPLIT_F16: return trans_p<PREC_SPLIT_F16>(p, v);
+    default: return false;
+    }
+}
+
 template <int P, int PREC>
 int count_variants()
 {
@@ -286,6 +341,7 @@ constexpr int default_variant(int p, int fam, int mode)
 {
     if (is_prism(p)) return 0;
     if (p == 1 && mode == 0) return trilinear_variant(p, fam);
+    if (p == 4 && mode == 2 && fam == MF_K16) return 4;  // tile 3 that also writes transposed blocks
     constexpr int f64[8] = {0, 0, 1, 1, 1, 1, 1, 1};
     if (fam == MF_F64) return f64[p];
     constexpr int k16[8] = {0, 3, 2, 1, 3, 4, 4, 4};
