@@ -7,8 +7,9 @@ default tile variant of each degree and precision, the default mixed-degree stra
   printed;
 * p = 5..7: seeded samples (48, 24, 16 elements, plus the first and the last), one oracle run
   per degree shared by the precisions;
-* the mixed-degree batch of 200000 elements and the 50-step time-stepped replay of 100000
-  elements on their samples;
+* the mixed-degree batch of 200000 elements through both strategies (samples against the oracle;
+  with the same tiles the two strategies agree bit for bit on every element), and the 50-step
+  time-stepped replay of 100000 elements on its samples;
 * the limits: an output indexed past 2^31 entries, and meshes scaled by 1e-4 and 1e4.
 """
 import functools
@@ -146,17 +147,39 @@ def oracle_field_sample(w, field, idx):
 
 @pytest.mark.parametrize("prec", ["split_fp16", "fp32"])
 def test_mixed_degree_full_size(fem, prec):
+    """The 200000-element mixed-degree batch through both strategies (one persistent launch over
+    every degree; one launch per degree with the default tiles): 256 seeded elements of each
+    against the oracle. With the per-degree launches set to the single launch's tiles, the two
+    strategies agree bit for bit on every element."""
     import torch
     w = synth.make(4)
     g, c, f, d = to_dev(w.geom, w.coef, w.field, w.degree)
-    A, b, a_off, b_off = fem.integrate_mixed(g, c, d, precision=prec, mode=fem.FIELD, field=f)
-    torch.cuda.synchronize()
-    idx = sample(w.nel, 24, 7)
-    ea, eb = packed_errors(A, b, a_off.cpu().numpy(), b_off.cpu().numpy(), w, idx,
-                           oracle_field_sample(w, w.field, idx))
-    log(f"[fullsize] mixed prec={prec} nel={w.nel} strategy={fem.fem_get_variant(0, fem.PRECISIONS[prec], fem.FIELD)} "
-        f"errA max={ea:.3e} errb max={eb:.3e}")
-    assert ea <= TOL_A[prec] and eb <= TOL_B[prec]
+    code = fem.PRECISIONS[prec]
+    saved = {p: fem.fem_get_variant(p, code, fem.FIELD) for p in range(8)}
+    idx = sample(w.nel, 256, 7)
+    ref = oracle_field_sample(w, w.field, idx)
+    try:
+        single = None
+        for strategy, name in ((0, "single_launch"), (1, "per_degree_launches")):
+            fem.fem_set_variant(0, code, fem.FIELD, strategy)
+            print(f"[fullsize] mixed prec={prec} strategy={name}", flush=True)
+            A, b, a_off, b_off = fem.integrate_mixed(g, c, d, precision=prec, mode=fem.FIELD, field=f)
+            torch.cuda.synchronize()
+            ea, eb = packed_errors(A, b, a_off.cpu().numpy(), b_off.cpu().numpy(), w, idx, ref)
+            log(f"[fullsize] mixed prec={prec} nel={w.nel} strategy={name} errA max={ea:.3e} errb max={eb:.3e}")
+            assert ea <= TOL_A[prec] and eb <= TOL_B[prec]
+            if strategy == 0:
+                single = (A, b)
+            del A, b
+        for p in range(1, 8):
+            fem.fem_set_variant(p, code, fem.FIELD, fem.mixed_tile_variant(p, code))
+        print(f"[fullsize] mixed prec={prec} per-degree launches with the single launch's tiles", flush=True)
+        A, b, _, _ = fem.integrate_mixed(g, c, d, precision=prec, mode=fem.FIELD, field=f)
+        torch.cuda.synchronize()
+        assert torch.equal(A, single[0]) and torch.equal(b, single[1])
+    finally:
+        for p, v in saved.items():
+            fem.fem_set_variant(p, code, fem.FIELD, v)
 
 
 def test_time_steps_full_size(fem):
