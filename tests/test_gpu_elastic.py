@@ -99,3 +99,30 @@ def test_elastic_blocks_are_transposes(fem, p, prec):
             up, low = A[:, i, k], A[:, k, i].transpose(0, 2, 1)
             err = np.linalg.norm(up - low, axis=(1, 2)) / np.linalg.norm(A.reshape(len(A), -1), axis=1)
             assert err.max() <= TOL_A[prec], (i, k, err.max())
+
+
+@pytest.mark.parametrize("prec", ["split_fp16", "bf16"])
+def test_lower_blocks_every_tile(fem, prec):
+    """p = 4 on the 16-bit paths: the default ELASTIC tile writes the lower blocks transposed
+    from its epilogue; every other tile (which cannot) falls back to the copy kernel. All give
+    the oracle's blocks, and the lower blocks equal the transposed upper ones bit for bit."""
+    import torch
+    p = 4
+    geom, coef, A_ref, _, _ = elastic_case(p)
+    g, c = to_dev(geom, coef)
+    code = fem.PRECISIONS[prec]
+    saved = fem.fem_get_variant(p, code, fem.ELASTIC)
+    try:
+        for v in range(fem.fem_variant_count(p, code)):
+            fem.fem_set_variant(p, code, fem.ELASTIC, v)
+            print(f"[elastic-tiles] p={p} prec={prec} v={v}", flush=True)
+            A, _ = fem.integrate(g, c, p, precision=prec, mode=fem.ELASTIC)
+            torch.cuda.synchronize()
+            for i in range(3):
+                for k in range(i + 1, 3):
+                    assert torch.equal(A[:, k, i], A[:, i, k].transpose(1, 2)), (v, i, k)
+            ea = rel_fro(full(A.double().cpu().numpy()), full(A_ref))
+            log(f"[elastic-tiles] p={p} prec={prec} v={v} errA max={ea.max():.3e}")
+            assert ea.max() <= TOL_A[prec]
+    finally:
+        fem.fem_set_variant(p, code, fem.ELASTIC, saved)
