@@ -516,7 +516,15 @@ def bench_mixed(args, torch, fem, synth, dev, quick=False):
         g, c, f, d, ws, a_off, b_off, A, b = mixed_buffers(torch, fem, w, dev, prec)
         a_np = a_off.cpu().numpy()
         code = fem.PRECISIONS[prec]
-        saved = fem.fem_get_variant(0, code, fem.FIELD)
+        keys = [0] + [fem.mixed(p) for p in range(1, 8)]
+        saved = {k: fem.fem_get_variant(k, code, fem.FIELD) for k in keys}
+        # the autotuner chooses the tile of every degree inside the single launch (on its own
+        # seeded batch of the same size and degree mix), then the strategy
+        t0 = time.time()
+        tuned, tune_ms = fem.fem_autotune(0, code, fem.FIELD, w.nel, None)
+        tiles = {str(p): fem.fem_mixed_variant(p, code, fem.FIELD) for p in range(1, 8)}
+        log(f"[bench] mixed {prec}: autotune {time.time() - t0:.1f} s, tiles {tiles}, strategy {tuned} "
+            f"(tuning batch ms {['%.2f' % x for x in tune_ms]})")
         for strategy, name in ((0, "single_launch"), (1, "per_degree_launches")):
             fem.fem_set_variant(0, code, fem.FIELD, strategy)
             call = lambda: fem.integrate_mixed(g, c, d, precision=prec, mode=fem.FIELD, field=f,
@@ -526,8 +534,12 @@ def bench_mixed(args, torch, fem, synth, dev, quick=False):
             fl = flops / (ms * 1e-3) / 1e12
             res[f"{prec}/{name}"] = {"ms": round(ms, 3), "el_per_s": w.nel / (ms * 1e-3),
                                      "tflops": round(fl, 2), "rel_err": st}
+            if strategy == 0:
+                res[f"{prec}/{name}"]["tiles"] = tiles  # per-degree variant run inside the launch
             log(f"[bench] mixed {prec} {name}: {ms:.3f} ms, {fl:.1f} TFLOP/s, max err {st['max']:.2e}")
-        fem.fem_set_variant(0, code, fem.FIELD, saved)  # the strategy in force before the benchmark
+        res[f"{prec}/autotuned_strategy"] = ["single_launch", "per_degree_launches"][tuned]
+        for k, v in saved.items():  # the choices in force before the benchmark
+            fem.fem_set_variant(k, code, fem.FIELD, v)
         del A, b
         torch.cuda.empty_cache()
     best = min(res["split_fp16/single_launch"]["ms"], res["split_fp16/per_degree_launches"]["ms"])

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define FEM_ABI_VERSION 3
+#define FEM_ABI_VERSION 4
 
 typedef enum {
     FEM_OK = 0,
@@ -267,15 +267,22 @@ int fem_reference_tables(int p, double *gauss_x, double *gauss_w, double *lobatt
  * default there; FIELD and ELASTIC calls use the tile variants.
  * p = 0 addresses the mixed-degree path (fem_integrate with p == 0), which has two variants:
  * 0 integrates every degree in one persistent launch (the work items of all degrees form one
- * index space, heaviest degree first, each degree with a fixed tile configuration); 1 (the
- * default) issues one launch per degree, each with the variant chosen for that degree. */
+ * index space, heaviest degree first; 256-thread workgroups throughout, each degree with the
+ * tile chosen for it under key FEM_MIXED(p)); 1 (the default) issues one launch per degree, each
+ * with the variant chosen for that degree.
+ * FEM_MIXED(p), p = 1..7, addresses the tile degree p runs with inside that single launch: one
+ * or two alternatives (variant 0 the default), each one of the 256-thread tile variants of the
+ * degree's own launches (fem_mixed_variant names it). */
 #define FEM_MAX_VARIANTS 6
 #define FEM_TRILINEAR_VARIANT(precision) ((precision) == FEM_FP64 ? 1 : 5)
 
 /* Variant keys of the prism of degree p (p = 1..7) in the calls below. */
 #define FEM_PRISM(p) (10 + (p))
 
-/* Number of variants compiled for (p, precision), p = 0..7 or FEM_PRISM(1..7) (>= 1),
+/* Variant keys of the tile of degree p (p = 1..7) inside the single mixed-degree launch. */
+#define FEM_MIXED(p) (20 + (p))
+
+/* Number of variants compiled for (p, precision), p = 0..7, FEM_PRISM(1..7) or FEM_MIXED(1..7) (>= 1),
  * FEM_EDEGREE or FEM_EINVAL (the work-assignment parameters of section 4.2 as compiled
  * alternatives). */
 int fem_variant_count(int p, int precision);
@@ -291,10 +298,11 @@ int fem_get_variant(int p, int precision, int mode);
  * variant computes the same result to the precision's tolerance. */
 int fem_set_variant(int p, int precision, int mode, int variant);
 
-/* The variant (tile configuration) that the single-launch mixed-degree kernel uses for degree
- * p = 1..7 and precision (section 4.2: per-degree parameters inside the one launch over all
- * degree classes); fixed at build time. FEM_EDEGREE / FEM_EINVAL on bad arguments. */
-int fem_mixed_variant(int p, int precision);
+/* The tile configuration, as a variant number of degree p's own launches, that the single-launch
+ * mixed-degree kernel currently runs degree p = 1..7 with for (precision, mode) (section 4.2:
+ * per-degree parameters inside the one launch over all degree classes; the alternative chosen
+ * under key FEM_MIXED(p)). FEM_EDEGREE / FEM_EINVAL on bad arguments. */
+int fem_mixed_variant(int p, int precision, int mode);
 
 /* Blocks of the elastostatics element matrix (section 5.1: 3 x 3 blocks of Ns x Ns) that an
  * ELASTIC call for degree p (1..7, or FEM_PRISM(1..7)) and precision integrates on the matrix
@@ -307,8 +315,12 @@ int fem_elastic_blocks(int p, int precision);
  * instead): time every variant on a seeded synthetic batch of nel elements in coefficient mode
  * `mode` (mildly distorted cubes; ELEMENT: CDR records, FIELD: rotations, loads and a seeded
  * field descriptor, ELASTIC: E, nu and body forces; for p = 0 degrees 1..7 drawn with weights
- * 8 - p, the timed call including the device bucketing; for p = FEM_PRISM(1..7) mildly
- * distorted prisms through fem_integrate_prism; ELASTIC needs p >= 1; 1 warm-up and 5
+ * 8 - p, the timed call including the device bucketing, after the tile of every degree inside
+ * the single launch has been tuned the same way (key FEM_MIXED(d) on a batch of about
+ * nel (8 - d) / 28 elements of degree d, recorded in the same file); for p = FEM_MIXED(d) a
+ * batch of degree d alone through the single mixed-degree launch; for p = FEM_PRISM(1..7)
+ * mildly distorted prisms through fem_integrate_prism; ELASTIC needs p = 1..7 or a prism
+ * key; 1 warm-up and 5
  * timed calls each, on a stream of its own), choose the fastest for (p, precision, mode), and,
  * if json_path is not NULL, record the choice and the times in that HOST file, keyed by
  * (architecture, p, precision, mode) (other entries of an existing file are kept). chosen

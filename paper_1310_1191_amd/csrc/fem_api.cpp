@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -292,12 +293,17 @@ int build_tables(State &st)
 
 namespace fem {
 // p = 0 addresses the mixed-degree path: variant 0 is the single persistent launch over every
-// degree, variant 1 one launch per degree.
+// degree, variant 1 one launch per degree. Keys MIXED_KEY + p (FEM_MIXED(p)) choose the tile
+// degree p runs with inside the single launch (mixed_tile alternatives 0, 1).
 constexpr int MIXED_SINGLE = 0, MIXED_PER_DEGREE = 1;
+constexpr int MIXED_KEY = 20;
+constexpr bool is_mixed_key(int p) { return p > MIXED_KEY && p <= MIXED_KEY + 7; }
+static_assert(FEM_MIXED(1) == MIXED_KEY + 1, "one numbering of the mixed-launch tile keys");
 
 int variant_count(int prec, int p)
 {
     if (p == 0) return 2;
+    if (is_mixed_key(p)) return prec >= PREC_F64 && prec <= PREC_SPLIT_F16 ? mixed_tile_count(p - MIXED_KEY, family_of(prec)) : 0;
     switch (prec) {
     case PREC_F64: return variants_f64(p);
     case PREC_F32: return variants_f32(p);
@@ -325,7 +331,9 @@ hipError_t dispatch_variant(int prec, int p, int v, const KArgs &a, hipStream_t 
 // strategy.
 constexpr int NMODES = 3;
 struct Choices {
-    int v[18][5][NMODES];  // [p] hexahedra (0: mixed strategy), [PRISM_BASE + p] prisms
+    // [p] hexahedra (0: mixed strategy), [PRISM_BASE + p] prisms, [MIXED_KEY + p] the tile of
+    // degree p inside the single mixed-degree launch
+    int v[MIXED_KEY + 8][5][NMODES];
     Choices()
     {
         for (int prec = 0; prec < 5; ++prec)
@@ -334,6 +342,7 @@ struct Choices {
                 for (int p = 1; p <= 7; ++p) {
                     v[p][prec][mode] = default_variant(p, family_of(prec), mode);
                     v[PRISM_BASE + p][prec][mode] = default_variant(PRISM_BASE + p, family_of(prec), mode);
+                    v[MIXED_KEY + p][prec][mode] = 0;
                 }
             }
     }
@@ -593,7 +602,9 @@ int integrate_impl(int64_t nel, int p, const double *geom, const fem_coeffs *coe
         ap.nel = nel;                  // upper bound; the bucket's count is read on the device
         ap.elist = plan.elist;
         ap.seg = plan.seg + 2 * pp;
+        m.tile[pp - 1] = g_choice.v[MIXED_KEY + pp][coeffs->precision][coeffs->mode];
     }
+    m.tile[7] = 0;
     if (g_choice.v[0][coeffs->precision][coeffs->mode] == MIXED_SINGLE)
         return dispatch_mixed(coeffs->precision, m, nel, s, g_cus) == hipSuccess ? FEM_OK : FEM_EHIP;
     for (int pp = 7; pp >= 1; --pp)  // heaviest degree first
@@ -791,8 +802,12 @@ bool write_tuning(const char *path, const std::string &arch, const std::vector<T
     return ok && std::rename(tmp.c_str(), path) == 0;
 }
 
-// Keys of the variant tables: 0 (the mixed-degree strategy), 1..7 (hexahedra), FEM_PRISM(1..7).
-bool valid_degree_key(int p) { return (p >= 0 && p <= 7) || (p > PRISM_BASE && p <= PRISM_BASE + 7); }
+// Keys of the variant tables: 0 (the mixed-degree strategy), 1..7 (hexahedra), FEM_PRISM(1..7),
+// FEM_MIXED(1..7) (the tile of a degree inside the single mixed-degree launch).
+bool valid_degree_key(int p)
+{
+    return (p >= 0 && p <= 7) || (p > PRISM_BASE && p <= PRISM_BASE + 7) || is_mixed_key(p);
+}
 
 }  // namespace
 
@@ -829,11 +844,11 @@ int fem_elastic_blocks(int p, int precision)
     return elastic_mode(p, precision) != E_NINE ? 6 : 9;
 }
 
-int fem_mixed_variant(int p, int precision)
+int fem_mixed_variant(int p, int precision, int mode)
 {
     if (p < 1 || p > 7) return FEM_EDEGREE;
-    if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16) return FEM_EINVAL;
-    return mixed_variant(p, family_of(precision));
+    if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16 || mode < 0 || mode >= NMODES) return FEM_EINVAL;
+    return mixed_tile(p, family_of(precision), g_choice.v[MIXED_KEY + p][precision][mode]);
 }
 
 int fem_autotune(int p, int precision, int mode, int64_t nel, const char *json_path, int *chosen,
@@ -843,8 +858,18 @@ int fem_autotune(int p, int precision, int mode, int64_t nel, const char *json_p
     if (!valid_degree_key(p)) return FEM_EDEGREE;
     if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16 || nel <= 0 || mode < 0 || mode >= NMODES)
         return FEM_EINVAL;
-    if (mode == FEM_COEF_ELASTIC && p == 0) return FEM_EINVAL;
-    const bool prism = is_prism(p);
+    if (mode == FEM_COEF_ELASTIC && (p == 0 || is_mixed_key(p))) return FEM_EINVAL;
+    // p = 0: first the tile of each degree inside the single launch, each on a batch of that
+    // degree alone of about the size its bucket has in the mix, then the strategy
+    if (p == 0)
+        for (int d = 7; d >= 1; --d) {
+            const int64_t nd = std::max<int64_t>(1, nel * (8 - d) / 28);
+            const int rc = fem_autotune(MIXED_KEY + d, precision, mode, nd, json_path, nullptr, nullptr);
+            if (rc != FEM_OK) return rc;
+        }
+    const bool mixed_tile_key = is_mixed_key(p);
+    const int dmix = mixed_tile_key ? p - MIXED_KEY : 0;  // the one degree of a tile key's batch
+    const bool prism = is_prism(p) && !mixed_tile_key;
     const int nv = variant_count(precision, p);
     const size_t osz = precision == FEM_FP64 ? 8 : 4;
     const int64_t blocks = mode == FEM_COEF_ELASTIC ? 9 : 1, comps = mode == FEM_COEF_ELASTIC ? 3 : 1;
@@ -864,13 +889,21 @@ int fem_autotune(int p, int precision, int mode, int64_t nel, const char *json_p
             a_off.push_back(a_off.back() + ns * ns);
             b_off.push_back(b_off.back() + ns);
         }
+    } else if (mixed_tile_key) {
+        deg.assign(size_t(nel), int8_t(dmix));
+        const int64_t ns = ns_of(dmix);
+        for (int64_t e = 0; e < nel; ++e) {
+            a_off.push_back(a_off.back() + ns * ns);
+            b_off.push_back(b_off.back() + ns);
+        }
     } else {
         a_off.push_back(nel * blocks * int64_t(ns_of(p)) * ns_of(p));
         b_off.push_back(nel * comps * int64_t(ns_of(p)));
     }
+    const bool via_mixed = p == 0 || mixed_tile_key;  // the call goes through the mixed-degree path
     void *d_geom = nullptr, *d_elem = nullptr, *d_field = nullptr, *d_A = nullptr, *d_b = nullptr;
     void *d_deg = nullptr, *d_aoff = nullptr, *d_boff = nullptr, *d_ws = nullptr;
-    const size_t ws_bytes = p == 0 ? mixed_workspace_bytes(nel) : 0;
+    const size_t ws_bytes = via_mixed ? mixed_workspace_bytes(nel) : 0;
     hipStream_t s = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     int rc = FEM_OK;
@@ -885,7 +918,7 @@ int fem_autotune(int p, int precision, int mode, int64_t nel, const char *json_p
         fail(FEM_ENOMEM);
     if (rc == FEM_OK && !tb.field.empty() && hipMalloc(&d_field, tb.field.size() * 8) != hipSuccess)
         fail(FEM_ENOMEM);
-    if (rc == FEM_OK && p == 0 &&
+    if (rc == FEM_OK && via_mixed &&
         (hipMalloc(&d_deg, nel) != hipSuccess || hipMalloc(&d_aoff, a_off.size() * 8) != hipSuccess ||
          hipMalloc(&d_boff, b_off.size() * 8) != hipSuccess || hipMalloc(&d_ws, ws_bytes) != hipSuccess))
         fail(FEM_ENOMEM);
@@ -899,7 +932,7 @@ int fem_autotune(int p, int precision, int mode, int64_t nel, const char *json_p
     if (rc == FEM_OK && d_field &&
         hipMemcpy(d_field, tb.field.data(), tb.field.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
         fail(FEM_EHIP);
-    if (rc == FEM_OK && p == 0 &&
+    if (rc == FEM_OK && via_mixed &&
         (hipMemcpy(d_deg, deg.data(), nel, hipMemcpyHostToDevice) != hipSuccess ||
          hipMemcpy(d_aoff, a_off.data(), a_off.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
          hipMemcpy(d_boff, b_off.data(), b_off.size() * 8, hipMemcpyHostToDevice) != hipSuccess))
@@ -916,13 +949,15 @@ int fem_autotune(int p, int precision, int mode, int64_t nel, const char *json_p
     c.workspace = d_ws;
     c.workspace_bytes = ws_bytes;
     const int saved = g_choice.v[p][precision][mode];
+    const int saved_strategy = g_choice.v[0][precision][mode];
     // each variant is timed through the whole call (every block of an elasticity call, the
-    // bucketing of a mixed-degree call)
+    // bucketing of a mixed-degree call); a tile key's through the single mixed-degree launch
     auto run = [&](int v) -> bool {
         g_choice.v[p][precision][mode] = v;
+        if (mixed_tile_key) g_choice.v[0][precision][mode] = MIXED_SINGLE;
         if (prism)
             return fem_integrate_prism(nel, deg_of(p), static_cast<const double *>(d_geom), &c, d_A, d_b, s) == FEM_OK;
-        return fem_integrate(nel, p, static_cast<const double *>(d_geom), &c, d_A, d_b, s) == FEM_OK;
+        return fem_integrate(nel, via_mixed ? 0 : p, static_cast<const double *>(d_geom), &c, d_A, d_b, s) == FEM_OK;
     };
     constexpr int REPS = 5;
     bool any = false;
@@ -946,6 +981,7 @@ int fem_autotune(int p, int precision, int mode, int64_t nel, const char *json_p
         any = true;
     }
     g_choice.v[p][precision][mode] = saved;
+    g_choice.v[0][precision][mode] = saved_strategy;
     if (ev[0]) (void)hipEventDestroy(ev[0]);
     if (ev[1]) (void)hipEventDestroy(ev[1]);
     if (s) (void)hipStreamDestroy(s);

@@ -1526,8 +1526,22 @@ k_integrate(const KArgs a)
 // index space that the persistent grid strides through; a workgroup handles its items of one
 // degree as a run (constants loaded once per run), then moves on to the next degree.
 struct MixedKArgs {
-    KArgs deg[7];  // deg[p - 1]: the bucket of degree p (seg = its {start, count})
+    KArgs deg[7];     // deg[p - 1]: the bucket of degree p (seg = its {start, count})
+    int32_t tile[8];  // tile[p - 1]: the tile alternative (0, 1) degree p runs with
 };
+
+// The arguments of degree d + 1, read from the kernel-argument segment (the launch's only
+// argument, a MixedKArgs, starts at its offset 0) through a pointer the compiler cannot see
+// through: a degree's arguments are then loaded where its segment uses them, instead of all
+// seven degrees' arguments being loaded at kernel entry and held in scalar registers (which
+// spills) for the whole launch.
+__device__ inline const KArgs &mixed_args(int d)
+{
+    typedef const __attribute__((address_space(4))) MixedKArgs *kptr;
+    kptr p = (kptr)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return *(const KArgs *)(&p->deg[d]);
+}
 
 template <int P, int PREC, class C, bool SUP>
 __device__ inline void mixed_segment(const KArgs &a, int64_t &base, unsigned char *smem)
@@ -1548,19 +1562,33 @@ __device__ inline void mixed_segment(const KArgs &a, int64_t &base, unsigned cha
     base += total;
 }
 
-template <int PREC, bool SUP, class C1, class C2, class C3, class C4, class C5, class C6, class C7>
+// Degree P's segment with the tile alternative the launch chose for it (uniform over the grid).
+template <int P, int PREC, class MT, bool SUP>
+__device__ inline void mixed_degree(const MixedKArgs &m, int64_t &base, unsigned char *smem)
+{
+    if constexpr (MT::template has_alt<P>()) {
+        if (m.tile[P - 1] != 0) {
+            mixed_segment<P, PREC, typename MT::template C<P, 1>, SUP>(mixed_args(P - 1), base, smem);
+            return;
+        }
+    }
+    mixed_segment<P, PREC, typename MT::template C<P, 0>, SUP>(mixed_args(P - 1), base, smem);
+}
+
+// MT: the tile set (MT::C<P, t>: alternative t of degree P; MT::has_alt<P>(): two alternatives).
+template <int PREC, bool SUP, class MT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 8)))
 k_integrate_mixed(const MixedKArgs m)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     int64_t base = 0;
-    mixed_segment<7, PREC, C7, SUP>(m.deg[6], base, smem);
-    mixed_segment<6, PREC, C6, SUP>(m.deg[5], base, smem);
-    mixed_segment<5, PREC, C5, SUP>(m.deg[4], base, smem);
-    mixed_segment<4, PREC, C4, SUP>(m.deg[3], base, smem);
-    mixed_segment<3, PREC, C3, SUP>(m.deg[2], base, smem);
-    mixed_segment<2, PREC, C2, SUP>(m.deg[1], base, smem);
-    mixed_segment<1, PREC, C1, SUP>(m.deg[0], base, smem);
+    mixed_degree<7, PREC, MT, SUP>(m, base, smem);
+    mixed_degree<6, PREC, MT, SUP>(m, base, smem);
+    mixed_degree<5, PREC, MT, SUP>(m, base, smem);
+    mixed_degree<4, PREC, MT, SUP>(m, base, smem);
+    mixed_degree<3, PREC, MT, SUP>(m, base, smem);
+    mixed_degree<2, PREC, MT, SUP>(m, base, smem);
+    mixed_degree<1, PREC, MT, SUP>(m, base, smem);
 }
 
 }  // namespace fem

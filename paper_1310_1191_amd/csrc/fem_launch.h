@@ -334,8 +334,7 @@ int variants_p(int p)
 }
 
 // Variant launched for each degree before any tuning (the fastest measured on MI355X at the
-// plain-method and high-order workload sizes), and the variant each degree uses inside the
-// single-launch mixed-degree kernel (256-thread workgroups only).
+// plain-method and high-order workload sizes).
 // p = 1 in ELEMENT mode (mode 0) runs the vector-ALU kernel.
 constexpr int default_variant(int p, int fam, int mode)
 {
@@ -348,27 +347,50 @@ constexpr int default_variant(int p, int fam, int mode)
     constexpr int f32[8] = {0, 4, 2, 1, 5, 4, 4, 4};
     return fam == MF_F32 ? f32[p] : k16[p];
 }
-constexpr int mixed_variant(int p, int fam)
+
+// The tiles compiled into the single-launch mixed-degree kernel: alternative t (0: the default,
+// 1: the other) of degree p, as a variant number of the per-degree launches, or -1 where a
+// degree has one. Only 256-thread tiles qualify (the kernel's workgroup size); the choice is made
+// per (degree, precision, coefficient mode) at run time.
+constexpr int mixed_tile(int p, int fam, int t)
 {
-    if (fam == MF_F64) return 0;
-    constexpr int m[8] = {0, 1, 3, 4, 3, 4, 4, 4};
-    return m[p];
+    constexpr int f64[2][8] = {{0, 0, 1, 1, 1, 1, 1, 1}, {0, -1, 0, 0, 0, 0, 0, 0}};
+    constexpr int k16[2][8] = {{0, 1, 1, 4, 3, 4, 4, 4}, {0, 0, 3, 2, 1, 1, 5, 1}};
+    return fam == MF_F64 ? f64[t][p] : k16[t][p];
 }
+constexpr int mixed_tile_count(int p, int fam) { return mixed_tile(p, fam, 1) >= 0 ? 2 : 1; }
+
+// The tile set of the single-launch mixed-degree kernel of a precision: C<P, t> is alternative t
+// of degree P (a degree with one alternative repeats it).
+template <int PREC>
+struct MixedTiles {
+    static constexpr int FAM = family_of(PREC);
+    template <int P> static constexpr bool has_alt() { return mixed_tile_count(P, FAM) == 2; }
+    template <int P, int T>
+    using C = typename VariantCfg<P, FAM, mixed_tile(P, FAM, has_alt<P>() ? T : 0)>::type;
+};
 
 // The single-launch mixed-degree kernel of a precision.
 template <int PREC>
 struct MixedInst {
-    template <int P> using CP = typename VariantCfg<P, family_of(PREC), mixed_variant(P, family_of(PREC))>::type;
-    template <int P> using SP = Shape<P, PREC, CP<P>>;
+    using MT = MixedTiles<PREC>;
+    template <int P, int T> using SP = Shape<P, PREC, typename MT::template C<P, T>>;
     static constexpr size_t max2(size_t x, size_t y) { return x > y ? x : y; }
+    template <int P> static constexpr size_t lds_p() { return max2(SP<P, 0>::lds_bytes, SP<P, 1>::lds_bytes); }
+    template <int P> static constexpr int64_t items_p()
+    {
+        return max2(SP<P, 0>::RT * SP<P, 0>::CT, SP<P, 1>::RT * SP<P, 1>::CT);
+    }
     static constexpr size_t lds_bytes =
-        max2(max2(max2(SP<1>::lds_bytes, SP<2>::lds_bytes), max2(SP<3>::lds_bytes, SP<4>::lds_bytes)),
-             max2(max2(SP<5>::lds_bytes, SP<6>::lds_bytes), SP<7>::lds_bytes));
+        max2(max2(max2(lds_p<1>(), lds_p<2>()), max2(lds_p<3>(), lds_p<4>())),
+             max2(max2(lds_p<5>(), lds_p<6>()), lds_p<7>()));
+    // work items per element, at most, over every degree and tile
+    static constexpr int64_t per_el = max2(max2(max2(items_p<1>(), items_p<2>()), max2(items_p<3>(), items_p<4>())),
+                                           max2(max2(items_p<5>(), items_p<6>()), items_p<7>()));
     static inline int resident_per_cu[2] = {1, 1};
     template <bool SUP> static const void *fn()
     {
-        return reinterpret_cast<const void *>(
-            &k_integrate_mixed<PREC, SUP, CP<1>, CP<2>, CP<3>, CP<4>, CP<5>, CP<6>, CP<7>>);
+        return reinterpret_cast<const void *>(&k_integrate_mixed<PREC, SUP, MT>);
     }
     template <bool SUP> static hipError_t prepare_one()
     {
@@ -392,22 +414,15 @@ struct MixedInst {
     // with the most items per element).
     static hipError_t launch(const MixedKArgs &m, int64_t nel, hipStream_t s, int cus)
     {
-        int64_t per_el = 1;
-        per_el = per_el > SP<7>::RT * SP<7>::CT ? per_el : SP<7>::RT * SP<7>::CT;
-        per_el = per_el > SP<6>::RT * SP<6>::CT ? per_el : SP<6>::RT * SP<6>::CT;
-        per_el = per_el > SP<5>::RT * SP<5>::CT ? per_el : SP<5>::RT * SP<5>::CT;
-        per_el = per_el > SP<4>::RT * SP<4>::CT ? per_el : SP<4>::RT * SP<4>::CT;
         const int64_t bound = nel * per_el;
         const bool sup = m.deg[0].jac != nullptr;
         const int64_t cap = int64_t(cus) * resident_per_cu[sup];
         const int64_t grid = bound < cap ? bound : cap;
         if (grid <= 0) return hipSuccess;
         if (sup)
-            hipLaunchKernelGGL((k_integrate_mixed<PREC, true, CP<1>, CP<2>, CP<3>, CP<4>, CP<5>, CP<6>, CP<7>>),
-                               dim3((unsigned)grid), dim3(256), lds_bytes, s, m);
+            hipLaunchKernelGGL((k_integrate_mixed<PREC, true, MT>), dim3((unsigned)grid), dim3(256), lds_bytes, s, m);
         else
-            hipLaunchKernelGGL((k_integrate_mixed<PREC, false, CP<1>, CP<2>, CP<3>, CP<4>, CP<5>, CP<6>, CP<7>>),
-                               dim3((unsigned)grid), dim3(256), lds_bytes, s, m);
+            hipLaunchKernelGGL((k_integrate_mixed<PREC, false, MT>), dim3((unsigned)grid), dim3(256), lds_bytes, s, m);
         return hipGetLastError();
     }
 };

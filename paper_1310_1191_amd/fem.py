@@ -107,7 +107,7 @@ def load():
     lib.fem_autotune.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                  ctypes.c_char_p, ctypes.POINTER(ctypes.c_int), dp]
     lib.fem_load_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]
-    lib.fem_mixed_variant.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.fem_mixed_variant.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.fem_elastic_blocks.argtypes = [ctypes.c_int, ctypes.c_int]
     _lib = lib
     return lib
@@ -182,6 +182,11 @@ PRISM_TRI_POINTS = {1: 3, 2: 6, 3: 12, 4: 16, 5: 25, 6: 33, 7: 42}
 def prism(p: int) -> int:
     """Variant key of the degree-p prism (FEM_PRISM(p))."""
     return 10 + int(p)
+
+
+def mixed(p: int) -> int:
+    """Variant key of degree p's tile inside the single mixed-degree launch (FEM_MIXED(p))."""
+    return 20 + int(p)
 
 
 def prism_ns(p: int) -> int:
@@ -278,8 +283,8 @@ def fem_autotune(p: int, precision: int, mode: int, nel: int, json_path: str | N
     return chosen.value, list(times)[:fem_variant_count(p, precision)]
 
 
-def fem_mixed_variant(p: int, precision: int) -> int:
-    rc = int(load().fem_mixed_variant(int(p), int(precision)))
+def fem_mixed_variant(p: int, precision: int, mode: int) -> int:
+    rc = int(load().fem_mixed_variant(int(p), int(precision), int(mode)))
     if rc < 0:
         raise FemError(rc, "fem_mixed_variant")
     return rc
@@ -293,8 +298,9 @@ def fem_elastic_blocks(p: int, precision: int) -> int:
     return rc
 
 
-def mixed_tile_variant(p: int, precision: int) -> int:
-    return fem_mixed_variant(p, precision)
+def mixed_tile_variant(p: int, precision: int, mode: int) -> int:
+    """The per-degree variant number of the tile degree p runs with in the single launch."""
+    return fem_mixed_variant(p, precision, mode)
 
 
 def fem_load_tuning(json_path: str) -> int:

@@ -38,7 +38,7 @@ def test_binding_wraps_every_symbol():
 
 def test_host_only_calls(lib):
     from paper_1310_1191_amd import fem
-    assert fem.fem_abi_version() == 3
+    assert fem.fem_abi_version() == 4
     assert fem.fem_strerror(0) == "success"
     assert "init" in fem.fem_strerror(fem.FEM_ENOTINIT)
     assert fem.fem_strerror(-99) == "unknown status"
@@ -139,6 +139,28 @@ def test_variant_table_host_calls(lib):
         assert fem.fem_variant_count(0, prec) == 2
         for m in fem.MODES:
             assert fem.fem_get_variant(0, prec, m) in (0, 1)
+    for p in range(1, 8):  # keys FEM_MIXED(p) = 20 + p: degree p's tile inside the single launch
+        for prec in range(5):
+            n = fem.fem_variant_count(fem.mixed(p), prec)
+            assert n == (1 if (p == 1 and prec == fem.PRECISIONS["fp64"]) else 2)
+            for m in fem.MODES:
+                assert fem.fem_get_variant(fem.mixed(p), prec, m) == 0
+            tiles = []
+            for t in range(n):
+                fem.fem_set_variant(fem.mixed(p), prec, fem.FIELD, t)
+                v = fem.fem_mixed_variant(p, prec, fem.FIELD)
+                assert 0 <= v < fem.fem_variant_count(p, prec)
+                assert p != 1 or v != fem.trilinear_variant(prec)  # a tile, not the vector kernel
+                tiles.append(v)
+            assert len(set(tiles)) == n  # the alternatives are distinct tiles
+            assert fem.fem_mixed_variant(p, prec, fem.ELEMENT) == tiles[0]  # per mode
+            fem.fem_set_variant(fem.mixed(p), prec, fem.FIELD, 0)
+            assert lib.fem_set_variant(fem.mixed(p), prec, fem.FIELD, n) == fem.FEM_ECONFIG
+    assert lib.fem_variant_count(20, 0) == fem.FEM_EDEGREE
+    assert lib.fem_variant_count(28, 0) == fem.FEM_EDEGREE
+    assert lib.fem_mixed_variant(0, 0, 0) == fem.FEM_EDEGREE
+    assert lib.fem_mixed_variant(8, 0, 0) == fem.FEM_EDEGREE
+    assert lib.fem_mixed_variant(3, 0, 3) == fem.FEM_EINVAL
     assert lib.fem_variant_count(-1, 0) == fem.FEM_EDEGREE
     assert lib.fem_variant_count(3, 5) == fem.FEM_EINVAL
     assert lib.fem_set_variant(8, 0, 0, 0) == fem.FEM_EDEGREE

@@ -172,7 +172,7 @@ def test_mixed_degree_full_size(fem, prec):
                 single = (A, b)
             del A, b
         for p in range(1, 8):
-            fem.fem_set_variant(p, code, fem.FIELD, fem.mixed_tile_variant(p, code))
+            fem.fem_set_variant(p, code, fem.FIELD, fem.mixed_tile_variant(p, code, fem.FIELD))
         print(f"[fullsize] mixed prec={prec} per-degree launches with the single launch's tiles", flush=True)
         A, b, _, _ = fem.integrate_mixed(g, c, d, precision=prec, mode=fem.FIELD, field=f)
         torch.cuda.synchronize()

@@ -120,19 +120,25 @@ def test_mixed_equals_uniform_launches_bitwise(fem, field_case):
             assert torch.equal(A[a_off[e]:a_off[e + 1]].view(ns, ns), Au[t]), (p, e)
 
 
-@pytest.mark.parametrize("prec", ["split_fp16", "fp64"])
-def test_single_launch_equals_per_degree_launches_bitwise(fem, prec):
-    """With the per-degree launches set to the tiles the single persistent launch uses, both
-    strategies give identical bits; a larger batch makes every workgroup handle several degrees
-    in turn."""
+@pytest.mark.parametrize("alt", [0, 1])
+@pytest.mark.parametrize("prec", ["split_fp16", "fp32", "fp64"])
+def test_single_launch_equals_per_degree_launches_bitwise(fem, prec, alt):
+    """With the per-degree launches set to the tiles the single persistent launch uses (its
+    default tiles, alt 0, or the other alternative of every degree, alt 1), both strategies give
+    identical bits; a larger batch makes every workgroup handle several degrees in turn."""
     import torch
     w = synth.make(4, grid=(16, 12, 10))        # 1920 elements, degrees 1..7
     g, c, f, d = to_dev(w.geom, w.coef, w.field, w.degree)
     code = fem.PRECISIONS[prec]
-    saved = {p: fem.fem_get_variant(p, code, fem.FIELD) for p in range(8)}
-    # per-degree launches with the tiles the single launch uses for each degree
+    keys = list(range(8)) + [fem.mixed(p) for p in range(1, 8)]
+    saved = {p: fem.fem_get_variant(p, code, fem.FIELD) for p in keys}
+    # the single launch's tile of each degree, and per-degree launches with the same tiles
+    tiles = {}
     for p in range(1, 8):
-        fem.fem_set_variant(p, code, fem.FIELD, fem.mixed_tile_variant(p, code))
+        fem.fem_set_variant(fem.mixed(p), code, fem.FIELD, min(alt, fem.fem_variant_count(fem.mixed(p), code) - 1))
+        tiles[p] = fem.mixed_tile_variant(p, code, fem.FIELD)
+        fem.fem_set_variant(p, code, fem.FIELD, tiles[p])
+    print(f"[mixed-bitwise] prec={prec} alt={alt} tiles={tiles}", flush=True)
     out = []
     for strategy in (0, 1):
         fem.fem_set_variant(0, code, fem.FIELD, strategy)
@@ -141,6 +147,6 @@ def test_single_launch_equals_per_degree_launches_bitwise(fem, prec):
         out.append((A, b))
     for p, v in saved.items():
         fem.fem_set_variant(p, code, fem.FIELD, v)
-    log(f"[mixed] {prec}: single vs per-degree, {w.nel} elements")
+    log(f"[mixed] {prec} tiles {tiles}: single vs per-degree, {w.nel} elements")
     assert torch.equal(out[0][0], out[1][0])
     assert torch.equal(out[0][1], out[1][1])

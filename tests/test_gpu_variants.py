@@ -64,10 +64,12 @@ def test_set_variant_rejects_missing_variant(fem):
 
 def test_autotune_writes_and_reloads_choice(fem, tmp_path):
     """Tuning per (degree, precision, coefficient mode): ELEMENT, FIELD and ELASTIC batches, the
-    mixed-degree strategy, the JSON file keyed by mode, and its reload."""
+    mixed-degree strategy (after the tile of every degree inside the single launch, keys
+    FEM_MIXED(d), recorded in the same file), the JSON file keyed by mode, and its reload."""
     path = tmp_path / "tuning.json"
     seen = {}
-    saved = {(p, c, m): fem.fem_get_variant(p, c, m) for p in range(8) for c in range(5) for m in fem.MODES}
+    keys = list(range(8)) + [fem.mixed(d) for d in range(1, 8)]
+    saved = {(p, c, m): fem.fem_get_variant(p, c, m) for p in keys for c in range(5) for m in fem.MODES}
     cases = [(2, fem.SPLIT_FP16, fem.ELEMENT), (4, fem.SPLIT_FP16, fem.ELEMENT), (3, fem.FP64, fem.ELEMENT),
              (0, fem.SPLIT_FP16, fem.ELEMENT), (3, fem.SPLIT_FP16, fem.FIELD), (0, fem.FP32, fem.FIELD),
              (2, fem.SPLIT_FP16, fem.ELASTIC), (1, fem.FP32, fem.ELEMENT), (1, fem.FP32, fem.FIELD)]
@@ -86,11 +88,15 @@ def test_autotune_writes_and_reloads_choice(fem, tmp_path):
         assert fem.fem_get_variant(p, prec, mode) == v
         assert {m: fem.fem_get_variant(p, prec, m) for m in other} == other  # other modes untouched
         seen[(p, prec, mode)] = v
+        if p == 0:
+            for d in range(1, 8):
+                seen[(fem.mixed(d), prec, mode)] = fem.fem_get_variant(fem.mixed(d), prec, mode)
     doc = json.loads(path.read_text())
     got = {(e["p"], e["precision"], e["mode"]): e["variant"] for e in doc["entries"]}
     assert got == seen
     for (p, prec, mode) in seen:
-        fem.fem_set_variant(p, prec, mode, (seen[(p, prec, mode)] + 1) % (fem.fem_variant_count(p, prec) - (p == 1)))
+        n = fem.fem_variant_count(p, prec) - (p == 1)  # p = 1: skip the vector-ALU variant
+        fem.fem_set_variant(p, prec, mode, (seen[(p, prec, mode)] + 1) % n)
     assert fem.fem_load_tuning(str(path)) == len(seen)
     for (p, prec, mode), v in seen.items():
         assert fem.fem_get_variant(p, prec, mode) == v
