@@ -243,6 +243,23 @@ int fem_mixed_offsets(int64_t nel, const int8_t *degree, int64_t *a_off, int64_t
 int fem_field_advance(double *field, const double *deltas, int32_t nsteps, int32_t *step,
                       void *stream);
 
+/* Gather a sample of the element matrices and load vectors into compact buffers, on the device
+ * (section 5.4, Tables 6-7: results travel back to the host after integration; in a replayed
+ * time step only a sample of them needs to). sel: [nrows][nsel] element ids; the row used is
+ * (*step - 1) mod nrows, the step counter that fem_field_advance moved on earlier in the same
+ * replay, or row 0 when step is NULL. a_off, b_off: the nel + 1 offsets of the source matrices
+ * and vectors (fem_mixed_offsets; element e's matrix is A[a_off[e] .. a_off[e + 1])). A, b: the
+ * outputs of fem_integrate in `precision`'s output type (FP64 for FEM_FP64, FP32 otherwise; b
+ * may be NULL, then out_b must be NULL too). out_A, out_b: the selected elements' matrices and
+ * vectors back to back in selection order, at most cap_A and cap_b entries written; ids outside
+ * [0, nel) are skipped and take no space. All pointers except the scalars are DEVICE pointers.
+ * Enqueues one kernel (nsel workgroups); allocates and synchronises nothing, so it can be
+ * captured with {fem_field_advance, fem_integrate}. FEM_EINVAL on bad arguments. */
+int fem_gather_sample(int64_t nsel, const int32_t *sel, int32_t nrows, const int32_t *step,
+                      int64_t nel, const int64_t *a_off, const int64_t *b_off, const void *A,
+                      const void *b, int precision, void *out_A, int64_t cap_A, void *out_b,
+                      int64_t cap_b, void *stream);
+
 /* HOST copies of the degree-p reference data the kernels use (section 2: quadrature points and
  * weights, and the 1-D factors of the shape functions): gauss_x[n], gauss_w[n] (the
  * (p+1)-point Gauss-Legendre rule), lobatto_x[n] (the nodes of the shape functions),

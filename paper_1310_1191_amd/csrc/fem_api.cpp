@@ -47,6 +47,10 @@ int variants_split_bf16(int p);
 int variants_split_f16(int p);
 hipError_t field_advance(double *field, const double *deltas, int32_t nsteps, int32_t *step,
                          hipStream_t s);
+hipError_t gather_sample(int64_t nsel, const int32_t *sel, int32_t nrows, const int32_t *step, int64_t nel,
+                         const int64_t *a_off, const int64_t *b_off, const void *A, const void *b,
+                         void *out_A, int64_t cap_A, void *out_b, int64_t cap_b, int32_t entry_bytes,
+                         hipStream_t s);
 void staged_release();
 }  // namespace fem
 
@@ -414,6 +418,24 @@ int fem_field_advance(double *field, const double *deltas, int32_t nsteps, int32
     if (!field || !step || nsteps < 0 || (nsteps > 0 && !deltas)) return FEM_EINVAL;
     return field_advance(field, deltas, nsteps, step, (hipStream_t)stream) == hipSuccess ? FEM_OK
                                                                                          : FEM_EHIP;
+}
+
+int fem_gather_sample(int64_t nsel, const int32_t *sel, int32_t nrows, const int32_t *step,
+                      int64_t nel, const int64_t *a_off, const int64_t *b_off, const void *A,
+                      const void *b, int precision, void *out_A, int64_t cap_A, void *out_b,
+                      int64_t cap_b, void *stream)
+{
+    if (!g_state.blob) return FEM_ENOTINIT;
+    if (precision < FEM_FP64 || precision > FEM_SPLIT_FP16) return FEM_EINVAL;
+    if (nsel < 0 || nsel > INT32_MAX || nel < 0 || cap_A < 0 || cap_b < 0) return FEM_EINVAL;
+    if (nsel == 0) return FEM_OK;
+    if (!sel || nrows < 1 || !a_off || !A || !out_A) return FEM_EINVAL;
+    if ((b != nullptr) != (out_b != nullptr) || (b && !b_off)) return FEM_EINVAL;
+    const int32_t entry_bytes = precision == FEM_FP64 ? 8 : 4;
+    return gather_sample(nsel, sel, nrows, step, nel, a_off, b_off, A, b, out_A, cap_A, out_b, cap_b,
+                         entry_bytes, (hipStream_t)stream) == hipSuccess
+               ? FEM_OK
+               : FEM_EHIP;
 }
 
 int fem_reference_tables(int p, double *gauss_x, double *gauss_w, double *lobatto_x, double *L,

@@ -101,6 +101,8 @@ def load():
     dp = ctypes.POINTER(ctypes.c_double)
     lib.fem_reference_tables.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp]
     lib.fem_field_advance.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
+    lib.fem_gather_sample.argtypes = [ctypes.c_int64, vp, ctypes.c_int32, vp, ctypes.c_int64, vp, vp,
+                                      vp, vp, ctypes.c_int, vp, ctypes.c_int64, vp, ctypes.c_int64, vp]
     lib.fem_variant_count.argtypes = [ctypes.c_int, ctypes.c_int]
     lib.fem_get_variant.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.fem_set_variant.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
@@ -119,7 +121,7 @@ def exported_symbols():
             "fem_abi_version", "fem_variant_count", "fem_get_variant", "fem_set_variant",
             "fem_autotune", "fem_load_tuning", "fem_mixed_variant", "fem_jacobian_terms",
             "fem_integrate_staged", "fem_integrate_noalloc", "fem_integrate_prism",
-            "fem_prism_reference_tables", "fem_elastic_blocks"]
+            "fem_prism_reference_tables", "fem_elastic_blocks", "fem_gather_sample"]
 
 
 # ---------------------------------------------------------------------------------------------
@@ -237,6 +239,12 @@ def fem_integrate_staged(nel: int, p: int, geom: int, coeffs: fem_coeffs, out_A:
 
 def fem_field_advance(field: int, deltas: int, nsteps: int, step: int, stream: int | None) -> int:
     return int(load().fem_field_advance(field, deltas, int(nsteps), step, stream))
+
+
+def fem_gather_sample(nsel, sel, nrows, step, nel, a_off, b_off, A, b, precision, out_A, cap_A,
+                      out_b, cap_b, stream) -> int:
+    return int(load().fem_gather_sample(int(nsel), sel, int(nrows), step, int(nel), a_off, b_off, A, b,
+                                        int(precision), out_A, int(cap_A), out_b, int(cap_b), stream))
 
 
 MAX_VARIANTS = 6
@@ -560,6 +568,34 @@ def jacobian_terms(geom, p: int = 0, degree=None, b_off=None, out=None, stream=N
     if rc != FEM_OK:
         raise FemError(rc, "fem_jacobian_terms")
     return out
+
+
+def gather_sample(sel, a_off, A, out_A, precision, b_off=None, b=None, out_b=None, step=None,
+                  stream=None):
+    """Copy the element matrices (and vectors) of one row of `sel` into out_A (out_b), back to back
+    in selection order (see fem_gather_sample). sel: int32 [nrows, nsel] (or [nsel]); the row
+    used is (step - 1) mod nrows with a step counter, else 0."""
+    torch = _torch()
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(sel, torch.int32, "sel")
+    _check(a_off, torch.int64, "a_off")
+    dt = out_dtype(prec)
+    _check(A, dt, "A")
+    _check(out_A, dt, "out_A")
+    if step is not None:
+        _check(step, torch.int32, "step")
+    if b is not None:
+        _check(b, dt, "b")
+        _check(out_b, dt, "out_b")
+        _check(b_off, torch.int64, "b_off", shape=tuple(a_off.shape))
+    nrows, nsel = (1, sel.shape[0]) if sel.dim() == 1 else (sel.shape[0], sel.shape[1])
+    rc = fem_gather_sample(nsel, _ptr(sel), nrows, _ptr(step) if step is not None else None,
+                           a_off.shape[0] - 1, _ptr(a_off), _ptr(b_off) if b_off is not None else None,
+                           _ptr(A), _ptr(b) if b is not None else None, prec, _ptr(out_A),
+                           out_A.numel(), _ptr(out_b) if out_b is not None else None,
+                           out_b.numel() if out_b is not None else 0, _stream(stream))
+    if rc != FEM_OK:
+        raise FemError(rc, "fem_gather_sample")
 
 
 def field_advance(field, deltas, step, stream=None):

@@ -52,6 +52,8 @@ def test_calls_before_init_are_rejected_on_the_host(lib):
     c = fem.fem_coeffs()
     assert fem.fem_integrate(10, 3, None, c, None, None, None) == fem.FEM_ENOTINIT
     assert fem.fem_mixed_offsets(10, None, None, None, None, 0, None) == fem.FEM_ENOTINIT
+    assert fem.fem_gather_sample(1, None, 1, None, 1, None, None, None, None, 0, None, 0, None, 0,
+                                 None) == fem.FEM_ENOTINIT
     assert lib.fem_finalize() == fem.FEM_ENOTINIT
 
 

@@ -1,6 +1,7 @@
 """Time-stepped re-integration: the device phase update matches the host recipe, and a captured
-{phase update, mixed-degree integration} graph replays step after step, each step matching the
-FP64 oracle on a sample of elements and the eager launches bit for bit."""
+{phase update, mixed-degree integration, sample gather} graph replays step after step, each step
+matching the FP64 oracle on the gathered sample and the eager launches bit for bit; the gather on
+its own (selection rows, skipped ids, capacity)."""
 import numpy as np
 import pytest
 
@@ -53,10 +54,17 @@ def test_graph_replay_time_steps(fem):
     b = torch.empty(int(b_off[-1].item()), dtype=torch.float32, device="cuda")
     a_np = a_off.cpu().numpy()
 
+    # each step's first three sampled elements, gathered on the device inside the replay
+    samples = [synth.step_sample(w.seed, t + 1, w.nel)[:3] for t in range(nsteps)]
+    sel = torch.from_numpy(np.stack(samples).astype(np.int32)).cuda()
+    cap = max(sum(int(a_np[e + 1] - a_np[e]) for e in idx) for idx in samples)
+    gathered = torch.empty(cap, dtype=torch.float32, device="cuda")
+
     def one_step(stream=None):
         fem.field_advance(f, dl, step, stream=stream)
         fem.integrate_mixed(g, c, d, precision="split_fp16", mode=fem.FIELD, field=f, a_off=a_off,
                             b_off=b_off, out_A=A, out_b=b, workspace=ws, stream=stream)
+        fem.gather_sample(sel, a_off, A, gathered, "split_fp16", step=step, stream=stream)
 
     # eager reference run of all steps
     eager = []
@@ -83,15 +91,60 @@ def test_graph_replay_time_steps(fem):
         graph.replay()
         torch.cuda.synchronize()
         assert torch.equal(A, eager[t]), f"replay {t} differs from the eager step"
-        # sampled oracle check of this step's coefficients
+        # sampled oracle check of this step's coefficients, on the matrices the replay gathered
         fld = synth.field_at_step(w.field, w.seed, t + 1)
-        idx = synth.step_sample(w.seed, t + 1, w.nel)[:3]
-        for e in idx:
+        got = gathered.double().cpu().numpy()
+        at = 0
+        for e in samples[t]:
             p = int(w.degree[e])
             ns = (p + 1) ** 3
+            assert torch.equal(gathered[at:at + ns * ns], A[a_np[e]:a_np[e + 1]])
             Ar, _, _ = oracle.integrate(w.geom[e:e + 1], w.coef[e:e + 1], p=p, mode=oracle.FIELD,
                                         field=fld)
-            Ag = A[a_np[e]:a_np[e + 1]].double().cpu().numpy().reshape(1, ns, ns)
+            Ag = got[at:at + ns * ns].reshape(1, ns, ns)
+            at += ns * ns
             err = rel_fro(Ag, Ar)[0]
             assert err <= TOL_A["split_fp16"], (t, e, err)
         log(f"[graph] step {t + 1}: replay == eager, sample ok")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "split_fp16"])
+def test_gather_sample(fem, prec):
+    """The gather copies the selected rows' matrices and vectors back to back in selection order
+    (the row picked by the step counter), skips ids outside the mesh, and writes nothing past the
+    capacity."""
+    import torch
+    w = synth.make(4, grid=(5, 4, 3))
+    g, c, f, d = to_dev(w.geom, w.coef, w.field, w.degree)
+    A, b, a_off, b_off = fem.integrate_mixed(g, c, d, precision=prec, mode=fem.FIELD, field=f)
+    torch.cuda.synchronize()
+    a_np, b_np = a_off.cpu().numpy(), b_off.cpu().numpy()
+    rng = np.random.default_rng(3)
+    rows = [rng.choice(w.nel, 9, replace=False).astype(np.int32) for _ in range(3)]
+    rows[1][4] = -1           # skipped
+    rows[2][0] = w.nel + 5    # skipped
+    sel = torch.from_numpy(np.stack(rows)).cuda()
+    dt = fem.out_dtype(prec)
+    for r in range(3):
+        step = torch.tensor([r + 1 + 3 * (r == 2)], dtype=torch.int32, device="cuda")  # row (step-1) % 3
+        valid = [int(e) for e in rows[r] if 0 <= e < w.nel]
+        na = sum(int(a_np[e + 1] - a_np[e]) for e in valid)
+        nb = sum(int(b_np[e + 1] - b_np[e]) for e in valid)
+        oa = torch.full((na + 7,), -1.0, dtype=dt, device="cuda")
+        ob = torch.full((nb + 7,), -1.0, dtype=dt, device="cuda")
+        print(f"[gather] prec={prec} row={r} n={len(valid)}", flush=True)
+        fem.gather_sample(sel, a_off, A, oa, prec, b_off=b_off, b=b, out_b=ob, step=step)
+        torch.cuda.synchronize()
+        refA = torch.cat([A[a_np[e]:a_np[e + 1]] for e in valid])
+        refb = torch.cat([b[b_np[e]:b_np[e + 1]] for e in valid])
+        assert torch.equal(oa[:na], refA) and torch.equal(ob[:nb], refb)
+        assert bool((oa[na:] == -1).all()) and bool((ob[nb:] == -1).all())
+    # capacity: a buffer one matrix short receives the leading entries only
+    valid = [int(e) for e in rows[0]]
+    na = sum(int(a_np[e + 1] - a_np[e]) for e in valid)
+    cut = na - int(a_np[valid[-1] + 1] - a_np[valid[-1]]) // 2
+    big = torch.full((na,), -1.0, dtype=dt, device="cuda")
+    fem.gather_sample(sel[0].contiguous(), a_off, A, big[:cut], prec)
+    torch.cuda.synchronize()
+    refA = torch.cat([A[a_np[e]:a_np[e + 1]] for e in valid])
+    assert torch.equal(big[:cut], refA[:cut]) and bool((big[cut:] == -1).all())
