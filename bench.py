@@ -145,6 +145,19 @@ def cpu_baseline(meshes, budget_s: float = 12.0):
             "gflops_fp64": sum(flops_per_element(p) * g.shape[0] for p, g, _ in meshes) / total_t / 1e9}
 
 
+def check_fractions(obj, path="line"):
+    """Every fraction of a peak in the record (keys "frac..."), at any depth, lies in [0, 1]: a
+    value above 1 means the counted work was not the work done."""
+    if isinstance(obj, dict):
+        for k, v in obj.items():
+            if k.startswith("frac") and isinstance(v, (int, float)) and not 0.0 <= v <= 1.0:
+                raise ValueError(f"{path}.{k} = {v}: a fraction of a peak outside [0, 1]")
+            check_fractions(v, f"{path}.{k}")
+    elif isinstance(obj, list):
+        for i, v in enumerate(obj):
+            check_fractions(v, f"{path}[{i}]")
+
+
 def err_stats(errs):
     """Max, 99th percentile and median of per-element relative errors."""
     e = np.asarray(errs, dtype=np.float64)
@@ -217,6 +230,7 @@ def main():
 
     if args.workload != "plain":
         line = WORKLOADS[args.workload](args, torch, fem, synth, dev)
+        check_fractions(line)
         print(json.dumps(line), flush=True)
         return
 
@@ -386,6 +400,7 @@ def main():
         "cpu_baseline": cpu,
         "extras": extras,
     }
+    check_fractions(line)
     print(json.dumps(line), flush=True)
 
 
