@@ -484,7 +484,8 @@ int fem_init(int device)
     hipError_t e;
     if ((e = prepare_f64()) != hipSuccess || (e = prepare_f32()) != hipSuccess ||
         (e = prepare_bf16()) != hipSuccess || (e = prepare_split_bf16()) != hipSuccess ||
-        (e = prepare_split_f16()) != hipSuccess || (e = mixed_prepare()) != hipSuccess)
+        (e = prepare_split_f16()) != hipSuccess || (e = mixed_prepare()) != hipSuccess ||
+        (e = transpose_prepare()) != hipSuccess)
         return FEM_EHIP;
     const int rc = build_tables(g_state);
     if (rc != FEM_OK) return rc;

@@ -9,4 +9,7 @@ namespace fem {
 // (i, k) in {(0, 1), (0, 2), (1, 2)}. Asynchronous on s; allocates nothing.
 hipError_t transpose_elastic_blocks(void *A, bool fp64, int64_t nel, int ns, hipStream_t s, int64_t cus);
 
+// Once per device, before the first transpose: allows the kernels' LDS staging above 64 KiB.
+hipError_t transpose_prepare();
+
 }  // namespace fem
