@@ -290,7 +290,7 @@ int fem_reference_tables(int p, double *gauss_x, double *gauss_w, double *lobatt
  * FEM_MIXED(p), p = 1..7, addresses the tile degree p runs with inside that single launch: one
  * or two alternatives (variant 0 the default), each one of the 256-thread tile variants of the
  * degree's own launches (fem_mixed_variant names it). */
-#define FEM_MAX_VARIANTS 6
+#define FEM_MAX_VARIANTS 7
 #define FEM_TRILINEAR_VARIANT(precision) ((precision) == FEM_FP64 ? 1 : 5)
 
 /* Variant keys of the prism of degree p (p = 1..7) in the calls below. */

@@ -103,8 +103,9 @@ struct Cfg {
     static constexpr int BT = BT_;    // PROD 1 only: 1 reads the B factors of the column operand
                                       // from a precomputed table instead of forming them from the
                                       // 1-D Lagrange tables
-    static constexpr int TE = TE_;    // 1: the per-wave staged epilogue can also write the block
-                                      // transposed (elasticity's lower blocks, KArgs::at_base)
+    static constexpr int TE = TE_;    // 1: the per-wave or whole-element staged epilogue can also
+                                      // write the block transposed (elasticity's lower blocks,
+                                      // KArgs::at_base), where Ns is odd
     static constexpr int NW = WGM_ * WGN_;
 };
 
@@ -200,7 +201,7 @@ struct Shape {
     // Tiles with TE can also write the transposed block (elasticity's lower blocks) from the
     // per-wave staged rows; with an odd Ns the column reads of the image are free of bank
     // conflicts. (A separate tile, so the other instances carry none of this code.)
-    static constexpr bool TRANS_EPI = C::TE && STAGE_WAVE && (NS % 2 == 1);
+    static constexpr bool TRANS_EPI = C::TE && (STAGE_WAVE || STAGE_OUT) && (NS % 2 == 1);
     static constexpr int WIMG = (TM * NS + 2 * VW - 1) / VW * VW;     // one row block
     // Otherwise a workgroup that owns whole elements with one row of waves stages one row block
     // of all its elements at a time.
@@ -1390,7 +1391,19 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
         for (int el = 0; el < neg; ++el) {
             const int64_t e = element_id(elist, e0 + el);
             OT *dst = outA + (a.a_off ? a.a_off[e] : a.a_base + e * a.a_stride);
-            copy_out(dst, s_out + el * S::IMG + img_shift(dst), NS * NS, tid, NT);
+            const OT *img = s_out + el * S::IMG + img_shift(dst);
+            copy_out(dst, img, NS * NS, tid, NT);
+            if constexpr (S::TRANS_EPI) {
+                // the transposed block (elastic lower block): entry x = c Ns + r of the copy is
+                // img[r Ns + c]; consecutive threads read LDS at the odd stride Ns
+                if (trans) {
+                    OT *dT = outA + a.at_base + e * a.a_stride;
+                    for (int x = tid; x < NS * NS; x += NT) {
+                        const int c = x / NS, r = x - c * NS;
+                        dT[x] = img[r * NS + c];
+                    }
+                }
+            }
         }
     } else {
 #pragma unroll

@@ -7,13 +7,14 @@
 
 namespace fem {
 
-constexpr int MAX_VARIANTS = 6;
+constexpr int MAX_VARIANTS = 7;
 
 // Cfg<EG, WGM, WGN, WM, WN, OCC, KC, RES, PROD> (see fem_kernel.h). For the 32-wide families
 // (FP32, BF16, split): p = 1 packs 16 elements of 8 trial functions into 4 column blocks
 // (variants 3, 4: the two k-groups of row fragments held in registers; variant 5 the
 // vector-ALU kernel of fem_trilinear.h, ELEMENT mode only);
-// p = 2, 3 put 4 (8) and 2 (4) elements side by side; p = 4 gives one element to a workgroup
+// p = 2, 3 put 4 (8) and 2 (4) elements side by side (p = 2 variant 6: variant 2 whose
+// epilogue also writes transposed elasticity blocks); p = 4 gives one element to a workgroup
 // (variant 3: one element to each wave, 4 x 4 blocks in registers); p >= 5 tile one element
 // into row x column tiles (variant 2: 4 x 4 blocks per wave). FP64 uses 16-wide blocks.
 template <int P, int FAM, int V> struct VariantCfg { using type = void; };
@@ -33,6 +34,7 @@ template <> struct VariantCfg<2, MF_K16, 2> { using type = Cfg<4, 1, 1, 1, 4, 2,
 template <> struct VariantCfg<2, MF_K16, 3> { using type = Cfg<4, 1, 4, 1, 1, 3, 1, 2, 1, 1>; };
 template <> struct VariantCfg<2, MF_K16, 4> { using type = Cfg<1, 1, 1, 1, 1, 3, 1, 2, 1, 1>; };
 template <> struct VariantCfg<2, MF_K16, 5> { using type = Cfg<2, 1, 1, 1, 2, 3, 1, 2, 1, 1>; };
+template <> struct VariantCfg<2, MF_K16, 6> { using type = Cfg<4, 1, 1, 1, 4, 2, 1, 2, 1, 1, 1>; };
 template <> struct VariantCfg<3, MF_K16, 0> { using type = Cfg<4, 1, 4, 2, 2, 3, 1, 2, 1, 1>; };
 template <> struct VariantCfg<3, MF_K16, 1> { using type = Cfg<8, 1, 8, 2, 2, 2, 1, 1, 1, 1>; };
 template <> struct VariantCfg<3, MF_K16, 2> { using type = Cfg<4, 1, 4, 2, 2, 2, 1, 2, 1>; };
@@ -188,7 +190,7 @@ hipError_t launch_variant(const KArgs &a, hipStream_t s, int cus)
 }
 
 // Whether a variant's epilogue can also write the transposed block (a.at_base, elasticity's
-// lower blocks): the per-wave staged epilogue with an odd Ns (Shape::TRANS_EPI).
+// lower blocks): the per-wave or whole-element staged epilogue with an odd Ns (Shape::TRANS_EPI).
 template <int P, int PREC, int V>
 constexpr bool trans_epilogue()
 {
@@ -206,6 +208,7 @@ bool trans_pv(int v)
     case 3: return trans_epilogue<P, PREC, 3>();
     case 4: return trans_epilogue<P, PREC, 4>();
     case 5: return trans_epilogue<P, PREC, 5>();
+    case 6: return trans_epilogue<P, PREC, 6>();
     default: return false;
     }
 }
@@ -246,7 +249,8 @@ template <int P, int PREC>
 int count_variants()
 {
     return has_variant<P, PREC, 0>() + has_variant<P, PREC, 1>() + has_variant<P, PREC, 2>() +
-           has_variant<P, PREC, 3>() + has_variant<P, PREC, 4>() + has_variant<P, PREC, 5>();
+           has_variant<P, PREC, 3>() + has_variant<P, PREC, 4>() + has_variant<P, PREC, 5>() +
+           has_variant<P, PREC, 6>();
 }
 
 template <int P, int PREC>
@@ -258,6 +262,7 @@ hipError_t prepare_p()
     if (e == hipSuccess) e = prepare_variant<P, PREC, 3>();
     if (e == hipSuccess) e = prepare_variant<P, PREC, 4>();
     if (e == hipSuccess) e = prepare_variant<P, PREC, 5>();
+    if (e == hipSuccess) e = prepare_variant<P, PREC, 6>();
     return e;
 }
 
@@ -285,6 +290,7 @@ hipError_t launch_pv(int v, const KArgs &a, hipStream_t s, int cus)
     case 3: return launch_variant<P, PREC, 3>(a, s, cus);
     case 4: return launch_variant<P, PREC, 4>(a, s, cus);
     case 5: return launch_variant<P, PREC, 5>(a, s, cus);
+    case 6: return launch_variant<P, PREC, 6>(a, s, cus);
     default: return hipErrorInvalidValue;
     }
 }
@@ -341,6 +347,7 @@ constexpr int default_variant(int p, int fam, int mode)
     if (is_prism(p)) return 0;
     if (p == 1 && mode == 0) return trilinear_variant(p, fam);
     if (p == 4 && mode == 2 && fam == MF_K16) return 4;  // tile 3 that also writes transposed blocks
+    if (p == 2 && mode == 2 && fam != MF_F64) return 6;  // tile 2 that also writes transposed blocks
     constexpr int f64[8] = {0, 0, 1, 1, 1, 1, 1, 1};
     if (fam == MF_F64) return f64[p];
     constexpr int k16[8] = {0, 3, 2, 1, 3, 4, 4, 4};

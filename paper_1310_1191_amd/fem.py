@@ -247,7 +247,7 @@ def fem_gather_sample(nsel, sel, nrows, step, nel, a_off, b_off, A, b, precision
                                         int(precision), out_A, int(cap_A), out_b, int(cap_b), stream))
 
 
-MAX_VARIANTS = 6
+MAX_VARIANTS = 7
 
 
 def trilinear_variant(precision: int) -> int:

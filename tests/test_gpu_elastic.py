@@ -101,14 +101,18 @@ def test_elastic_blocks_are_transposes(fem, p, prec):
             assert err.max() <= TOL_A[prec], (i, k, err.max())
 
 
-@pytest.mark.parametrize("prec", ["split_fp16", "bf16"])
-def test_lower_blocks_every_tile(fem, prec):
-    """p = 4 on the 16-bit paths: the default ELASTIC tile writes the lower blocks transposed
-    from its epilogue; every other tile (which cannot) falls back to the copy kernel. All give
-    the oracle's blocks, and the lower blocks equal the transposed upper ones bit for bit."""
+@pytest.mark.parametrize("p,prec", [(4, "split_fp16"), (4, "bf16"), (2, "split_fp16"), (2, "fp32"),
+                                    (2, "fp64")])
+def test_lower_blocks_every_tile(fem, p, prec):
+    """p = 4 on the 16-bit paths and p = 2 on the 32-wide ones: the default ELASTIC tile writes
+    the lower blocks transposed from its epilogue (per-wave staging at p = 4, whole-element
+    staging at p = 2); every other tile (which cannot), and FP64, falls back to the copy kernel.
+    All give the oracle's blocks, and the lower blocks equal the transposed upper ones bit for
+    bit."""
     import torch
-    p = 4
     geom, coef, A_ref, _, _ = elastic_case(p)
+    n = geom.shape[0] - 1  # a ragged last element group at p = 2 (4 elements per group)
+    geom, coef, A_ref = geom[:n], coef[:n], A_ref[:n]
     g, c = to_dev(geom, coef)
     code = fem.PRECISIONS[prec]
     saved = fem.fem_get_variant(p, code, fem.ELASTIC)
