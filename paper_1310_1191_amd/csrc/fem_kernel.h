@@ -198,15 +198,18 @@ struct Shape {
     static constexpr bool STAGE_OUT = (RT == 1 && CT == 1) && size_t(EG) * IMG * sizeof(OT) <= 65536 &&
                                       !(WAVE_OWNS_EL && C::NW == 1);
     static constexpr bool STAGE_WAVE = !STAGE_OUT && WAVE_OWNS_EL;
-    // Tiles with TE can also write the transposed block (elasticity's lower blocks) from the
-    // per-wave staged rows; with an odd Ns the column reads of the image are free of bank
-    // conflicts. (A separate tile, so the other instances carry none of this code.)
+    // Tiles with TE can also write the transposed block (elasticity's lower blocks): with an odd
+    // Ns from the staged image (its column reads then free of bank conflicts), with Ns a
+    // multiple of 4 on the 32-wide families straight from the accumulators, whose four
+    // consecutive rows per lane make one 16-byte run of a transposed row (per-wave staged and
+    // direct epilogues). (Separate tiles, so the other instances carry none of this code.)
     static constexpr bool TRANS_EPI = C::TE && (STAGE_WAVE || STAGE_OUT) && (NS % 2 == 1);
     static constexpr int WIMG = (TM * NS + 2 * VW - 1) / VW * VW;     // one row block
     // Otherwise a workgroup that owns whole elements with one row of waves stages one row block
     // of all its elements at a time.
     static constexpr bool STAGE_RB = !STAGE_OUT && !STAGE_WAVE && RT == 1 && CT == 1 && C::WGM == 1 &&
                                      size_t(EG) * WIMG * sizeof(OT) <= 65536;
+    static constexpr bool TRANS_REG = C::TE && FAM != MF_F64 && (NS % 4 == 0) && !STAGE_OUT;
     static constexpr size_t out_bytes = STAGE_OUT ? size_t(EG) * IMG * sizeof(OT)
                                       : STAGE_WAVE ? size_t(C::NW) * WIMG * sizeof(OT)
                                       : STAGE_RB ? size_t(EG) * WIMG * sizeof(OT) : 0;
@@ -1287,6 +1290,34 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
             if (rl < nrow) dT[(int64_t)c * NS + r0 + rl] = img[rl * NS + c];
         }
     };
+    // The transposed copy straight from one accumulator block (TRANS_REG): this lane's column jj
+    // of the block starting at row r0 becomes row jj of the transposed block; its accumulator
+    // entries 4g .. 4g + 3 are four consecutive rows, so one 16-byte store each (scalar stores
+    // where the destination is not 16-byte aligned).
+    auto write_t = [&](OT *dT, const typename F::acc &ac, int r0, int jj, float us) {
+        if constexpr (S::TRANS_REG) {
+            static_assert(std::is_same<OT, float>::value, "the 32-wide families write FP32");
+            if (jj >= NS) return;
+            OT *rowp = dT + (int64_t)jj * NS;
+            const bool vec = (reinterpret_cast<uintptr_t>(rowp) & 15) == 0;
+#pragma unroll
+            for (int g = 0; g < F::ACC_N / 4; ++g) {
+                const int row = r0 + acc_row<FAM>(lane, 4 * g);
+                if (row >= NS) continue;  // Ns % 4 == 0: all four rows are in range
+                const float v0 = ac[4 * g] * us, v1 = ac[4 * g + 1] * us, v2 = ac[4 * g + 2] * us,
+                            v3 = ac[4 * g + 3] * us;
+                if (vec) {
+                    f32x4 q = {v0, v1, v2, v3};
+                    *reinterpret_cast<f32x4 *>(rowp + row) = q;
+                } else {
+                    rowp[row] = v0;
+                    rowp[row + 1] = v1;
+                    rowp[row + 2] = v2;
+                    rowp[row + 3] = v3;
+                }
+            }
+        }
+    };
     if constexpr (S::STAGE_WAVE) {
         // This wave's element: column blocks cbt0 .. cbt0 + WN - 1 of the tile are its columns.
         const int el = (cbt0 * TM) / S::NSP;
@@ -1320,6 +1351,12 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
                 copy_out(dst, img, nrow * NS, lane, 64);
                 if constexpr (S::TRANS_EPI)
                     if (trans) copy_out_t(outA + a.at_base + e * a.a_stride, img, nrow, r0, lane, 64);
+                if constexpr (S::TRANS_REG)
+                    if (trans) {
+#pragma unroll
+                        for (int j = 0; j < C::WN; ++j)
+                            write_t(outA + a.at_base + e * a.a_stride, acc[i][j], r0, j * TM + (lane % TM), us);
+                    }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1350,6 +1387,8 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
                     if (rl < nrow)
                         img[rl * NS + jj] = (PREC == PREC_F64) ? OT(acc[i][j][v]) : OT(acc[i][j][v] * us);
                 }
+                if constexpr (S::TRANS_REG)
+                    if (trans) write_t(outA + a.at_base + e * a.a_stride, acc[i][j], r0, jj, us);
             }
             __syncthreads();
             for (int el = 0; el < neg; ++el) {
@@ -1428,6 +1467,8 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
                         else outA[base + (int64_t)row * NS + jj] = acc[i][j][v] * us;
                     }
                 }
+                if constexpr (S::TRANS_REG)
+                    if (trans) write_t(outA + a.at_base + e * a.a_stride, acc[i][j], (rb0 + i) * TM, jj, us);
             }
         }
     }

@@ -13,10 +13,11 @@ constexpr int MAX_VARIANTS = 7;
 // (FP32, BF16, split): p = 1 packs 16 elements of 8 trial functions into 4 column blocks
 // (variants 3, 4: the two k-groups of row fragments held in registers; variant 5 the
 // vector-ALU kernel of fem_trilinear.h, ELEMENT mode only);
-// p = 2, 3 put 4 (8) and 2 (4) elements side by side (p = 2 variant 6: variant 2 whose
-// epilogue also writes transposed elasticity blocks); p = 4 gives one element to a workgroup
+// p = 2, 3 put 4 (8) and 2 (4) elements side by side; p = 4 gives one element to a workgroup
 // (variant 3: one element to each wave, 4 x 4 blocks in registers); p >= 5 tile one element
-// into row x column tiles (variant 2: 4 x 4 blocks per wave). FP64 uses 16-wide blocks.
+// into row x column tiles (variant 2: 4 x 4 blocks per wave). FP64 uses 16-wide blocks. The
+// elasticity defaults p = 2, 3 variant 6, p = 4 variant 4 and p = 5, 7 variant 5 are the tiles
+// before them (2, 1, 3, 4, 4) whose epilogue also writes the transposed (lower) blocks.
 template <int P, int FAM, int V> struct VariantCfg { using type = void; };
 // The vector-ALU kernel of trilinear hexahedra (fem_trilinear.h; ELEMENT mode only).
 struct TrilinearCfg {};
@@ -41,6 +42,7 @@ template <> struct VariantCfg<3, MF_K16, 2> { using type = Cfg<4, 1, 4, 2, 2, 2,
 template <> struct VariantCfg<3, MF_K16, 3> { using type = Cfg<4, 1, 4, 2, 2, 2, 2, 0, 1>; };
 template <> struct VariantCfg<3, MF_K16, 4> { using type = Cfg<4, 1, 4, 2, 2, 2, 1, 2, 1, 1>; };
 template <> struct VariantCfg<3, MF_K16, 5> { using type = Cfg<1, 1, 1, 2, 2, 2, 1, 2, 1, 1>; };
+template <> struct VariantCfg<3, MF_K16, 6> { using type = Cfg<8, 1, 8, 2, 2, 2, 1, 1, 1, 1, 1>; };
 template <> struct VariantCfg<4, MF_K16, 0> { using type = Cfg<1, 1, 1, 4, 4, 1, 1, 0, 1, 0>; };
 template <> struct VariantCfg<4, MF_K16, 1> { using type = Cfg<2, 1, 4, 4, 2, 1, 1, 0, 1>; };
 template <> struct VariantCfg<4, MF_K16, 2> { using type = Cfg<2, 1, 4, 4, 2, 2, 1, 0, 1>; };
@@ -52,6 +54,7 @@ template <> struct VariantCfg<5, MF_K16, 1> { using type = Cfg<1, 1, 4, 4, 1, 1,
 template <> struct VariantCfg<5, MF_K16, 2> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1>; };
 template <> struct VariantCfg<5, MF_K16, 3> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1, 1>; };
 template <> struct VariantCfg<5, MF_K16, 4> { using type = Cfg<1, 1, 4, 7, 2, 1, 1, 0, 1>; };
+template <> struct VariantCfg<5, MF_K16, 5> { using type = Cfg<1, 1, 4, 7, 2, 1, 1, 0, 1, 0, 1>; };
 template <> struct VariantCfg<6, MF_K16, 0> { using type = Cfg<1, 1, 4, 6, 1, 1, 2, 0, 0>; };
 template <> struct VariantCfg<6, MF_K16, 1> { using type = Cfg<1, 1, 4, 6, 1, 1, 2, 0, 1>; };
 template <> struct VariantCfg<6, MF_K16, 2> { using type = Cfg<1, 3, 1, 4, 4, 1, 1, 0, 1>; };
@@ -63,6 +66,7 @@ template <> struct VariantCfg<7, MF_K16, 1> { using type = Cfg<1, 1, 4, 8, 1, 1,
 template <> struct VariantCfg<7, MF_K16, 2> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1>; };
 template <> struct VariantCfg<7, MF_K16, 3> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1, 1>; };
 template <> struct VariantCfg<7, MF_K16, 4> { using type = Cfg<1, 1, 4, 8, 2, 1, 1, 0, 1>; };
+template <> struct VariantCfg<7, MF_K16, 5> { using type = Cfg<1, 1, 4, 8, 2, 1, 1, 0, 1, 0, 1>; };
 // -- prisms (P = PRISM_BASE + p; Ns = 6, 18, 40, 75, 126, 196, 288): every variant produces the
 // column operand per wave from the B-factor table (PROD 1, BT 1). p = 1 packs 16 elements at a
 // pitch of 8 columns; p = 2, 3, 4 give one element to each wave (1 x 1, 2 x 2, 3 x 3 blocks);
@@ -190,13 +194,14 @@ hipError_t launch_variant(const KArgs &a, hipStream_t s, int cus)
 }
 
 // Whether a variant's epilogue can also write the transposed block (a.at_base, elasticity's
-// lower blocks): the per-wave or whole-element staged epilogue with an odd Ns (Shape::TRANS_EPI).
+// lower blocks): from the staged image with an odd Ns (Shape::TRANS_EPI), or from the
+// accumulators on the 32-wide families with Ns a multiple of 4 (Shape::TRANS_REG).
 template <int P, int PREC, int V>
 constexpr bool trans_epilogue()
 {
     using Cf = typename VariantCfg<P, family_of(PREC), V>::type;
     if constexpr (std::is_void<Cf>::value || std::is_same<Cf, TrilinearCfg>::value) return false;
-    else return Shape<P, PREC, Cf>::TRANS_EPI;
+    else return Shape<P, PREC, Cf>::TRANS_EPI || Shape<P, PREC, Cf>::TRANS_REG;
 }
 template <int P, int PREC>
 bool trans_pv(int v)
@@ -347,7 +352,11 @@ constexpr int default_variant(int p, int fam, int mode)
     if (is_prism(p)) return 0;
     if (p == 1 && mode == 0) return trilinear_variant(p, fam);
     if (p == 4 && mode == 2 && fam == MF_K16) return 4;  // tile 3 that also writes transposed blocks
-    if (p == 2 && mode == 2 && fam != MF_F64) return 6;  // tile 2 that also writes transposed blocks
+    if (mode == 2 && fam != MF_F64) {
+        // the default tiles' twins that also write the transposed (lower) blocks
+        if (p == 2 || p == 3) return 6;
+        if (p == 5 || p == 7) return 5;
+    }
     constexpr int f64[8] = {0, 0, 1, 1, 1, 1, 1, 1};
     if (fam == MF_F64) return f64[p];
     constexpr int k16[8] = {0, 3, 2, 1, 3, 4, 4, 4};
