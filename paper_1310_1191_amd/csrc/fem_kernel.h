@@ -199,17 +199,17 @@ struct Shape {
                                       !(WAVE_OWNS_EL && C::NW == 1);
     static constexpr bool STAGE_WAVE = !STAGE_OUT && WAVE_OWNS_EL;
     // Tiles with TE can also write the transposed block (elasticity's lower blocks): with an odd
-    // Ns from the staged image (its column reads then free of bank conflicts), with Ns a
-    // multiple of 4 on the 32-wide families straight from the accumulators, whose four
-    // consecutive rows per lane make one 16-byte run of a transposed row (per-wave staged and
-    // direct epilogues). (Separate tiles, so the other instances carry none of this code.)
+    // Ns from a staged image (its column reads then free of bank conflicts), otherwise on the
+    // 32-wide families straight from the accumulators, whose four consecutive rows per lane make
+    // one run of a transposed row (16-byte stores where Ns is a multiple of 4). (Separate
+    // tiles, so the other instances carry none of this code.)
     static constexpr bool TRANS_EPI = C::TE && (STAGE_WAVE || STAGE_OUT) && (NS % 2 == 1);
     static constexpr int WIMG = (TM * NS + 2 * VW - 1) / VW * VW;     // one row block
     // Otherwise a workgroup that owns whole elements with one row of waves stages one row block
     // of all its elements at a time.
     static constexpr bool STAGE_RB = !STAGE_OUT && !STAGE_WAVE && RT == 1 && CT == 1 && C::WGM == 1 &&
                                      size_t(EG) * WIMG * sizeof(OT) <= 65536;
-    static constexpr bool TRANS_REG = C::TE && FAM != MF_F64 && (NS % 4 == 0) && !STAGE_OUT;
+    static constexpr bool TRANS_REG = C::TE && FAM != MF_F64 && !STAGE_OUT && !TRANS_EPI;
     static constexpr size_t out_bytes = STAGE_OUT ? size_t(EG) * IMG * sizeof(OT)
                                       : STAGE_WAVE ? size_t(C::NW) * WIMG * sizeof(OT)
                                       : STAGE_RB ? size_t(EG) * WIMG * sizeof(OT) : 0;
@@ -1292,8 +1292,8 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
     };
     // The transposed copy straight from one accumulator block (TRANS_REG): this lane's column jj
     // of the block starting at row r0 becomes row jj of the transposed block; its accumulator
-    // entries 4g .. 4g + 3 are four consecutive rows, so one 16-byte store each (scalar stores
-    // where the destination is not 16-byte aligned).
+    // entries 4g .. 4g + 3 are four consecutive rows, so one 16-byte store each where the
+    // destination is 16-byte aligned and all four rows exist, else scalar stores.
     auto write_t = [&](OT *dT, const typename F::acc &ac, int r0, int jj, float us) {
         if constexpr (S::TRANS_REG) {
             static_assert(std::is_same<OT, float>::value, "the 32-wide families write FP32");
@@ -1303,17 +1303,17 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
 #pragma unroll
             for (int g = 0; g < F::ACC_N / 4; ++g) {
                 const int row = r0 + acc_row<FAM>(lane, 4 * g);
-                if (row >= NS) continue;  // Ns % 4 == 0: all four rows are in range
+                if (row >= NS) continue;
                 const float v0 = ac[4 * g] * us, v1 = ac[4 * g + 1] * us, v2 = ac[4 * g + 2] * us,
                             v3 = ac[4 * g + 3] * us;
-                if (vec) {
+                if (NS % 4 == 0 && vec) {  // Ns % 4 == 0: all four rows are in range
                     f32x4 q = {v0, v1, v2, v3};
                     *reinterpret_cast<f32x4 *>(rowp + row) = q;
                 } else {
                     rowp[row] = v0;
-                    rowp[row + 1] = v1;
-                    rowp[row + 2] = v2;
-                    rowp[row + 3] = v3;
+                    if (row + 1 < NS) rowp[row + 1] = v1;
+                    if (row + 2 < NS) rowp[row + 2] = v2;
+                    if (row + 3 < NS) rowp[row + 3] = v3;
                 }
             }
         }

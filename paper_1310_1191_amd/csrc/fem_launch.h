@@ -16,8 +16,8 @@ constexpr int MAX_VARIANTS = 7;
 // p = 2, 3 put 4 (8) and 2 (4) elements side by side; p = 4 gives one element to a workgroup
 // (variant 3: one element to each wave, 4 x 4 blocks in registers); p >= 5 tile one element
 // into row x column tiles (variant 2: 4 x 4 blocks per wave). FP64 uses 16-wide blocks. The
-// elasticity defaults p = 2, 3 variant 6, p = 4 variant 4 and p = 5, 7 variant 5 are the tiles
-// before them (2, 1, 3, 4, 4) whose epilogue also writes the transposed (lower) blocks.
+// elasticity defaults p = 2, 3, 6 variant 6, p = 4 variant 4 and p = 5, 7 variant 5 are the
+// tiles (2, 1, 4, 3, 4, 4) whose epilogue also writes the transposed (lower) blocks.
 template <int P, int FAM, int V> struct VariantCfg { using type = void; };
 // The vector-ALU kernel of trilinear hexahedra (fem_trilinear.h; ELEMENT mode only).
 struct TrilinearCfg {};
@@ -61,6 +61,7 @@ template <> struct VariantCfg<6, MF_K16, 2> { using type = Cfg<1, 3, 1, 4, 4, 1,
 template <> struct VariantCfg<6, MF_K16, 3> { using type = Cfg<1, 3, 1, 4, 4, 1, 1, 0, 1, 1>; };
 template <> struct VariantCfg<6, MF_K16, 4> { using type = Cfg<1, 1, 4, 11, 1, 1, 1, 0, 1>; };
 template <> struct VariantCfg<6, MF_K16, 5> { using type = Cfg<1, 4, 1, 3, 4, 1, 1, 0, 1>; };
+template <> struct VariantCfg<6, MF_K16, 6> { using type = Cfg<1, 1, 4, 11, 1, 1, 1, 0, 1, 0, 1>; };
 template <> struct VariantCfg<7, MF_K16, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 2, 0, 0>; };
 template <> struct VariantCfg<7, MF_K16, 1> { using type = Cfg<1, 1, 4, 8, 1, 1, 2, 0, 1>; };
 template <> struct VariantCfg<7, MF_K16, 2> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1>; };
@@ -195,7 +196,7 @@ hipError_t launch_variant(const KArgs &a, hipStream_t s, int cus)
 
 // Whether a variant's epilogue can also write the transposed block (a.at_base, elasticity's
 // lower blocks): from the staged image with an odd Ns (Shape::TRANS_EPI), or from the
-// accumulators on the 32-wide families with Ns a multiple of 4 (Shape::TRANS_REG).
+// accumulators on the 32-wide families (Shape::TRANS_REG).
 template <int P, int PREC, int V>
 constexpr bool trans_epilogue()
 {
@@ -354,7 +355,7 @@ constexpr int default_variant(int p, int fam, int mode)
     if (p == 4 && mode == 2 && fam == MF_K16) return 4;  // tile 3 that also writes transposed blocks
     if (mode == 2 && fam != MF_F64) {
         // the default tiles' twins that also write the transposed (lower) blocks
-        if (p == 2 || p == 3) return 6;
+        if (p == 2 || p == 3 || p == 6) return 6;
         if (p == 5 || p == 7) return 5;
     }
     constexpr int f64[8] = {0, 0, 1, 1, 1, 1, 1, 1};
