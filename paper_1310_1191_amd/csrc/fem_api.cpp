@@ -87,7 +87,7 @@ int64_t g_cus = 256;  // compute units of the device (persistent grids: CUs x re
 // launch from the tile it stages anyway (E_EPI, no re-read of the block). Measured on MI355X.
 enum ElasticMode { E_NINE = 0, E_COPY = 1, E_EPI = 2 };
 constexpr int ELASTIC_MODE_K16[8] = {E_NINE, E_NINE, E_EPI, E_EPI, E_EPI, E_EPI, E_EPI, E_EPI};
-constexpr int ELASTIC_MODE_WIDE[8] = {E_NINE, E_NINE, E_EPI, E_EPI, E_COPY, E_EPI, E_EPI, E_EPI};
+constexpr int ELASTIC_MODE_WIDE[8] = {E_NINE, E_NINE, E_EPI, E_EPI, E_EPI, E_EPI, E_EPI, E_EPI};
 int elastic_mode(int P, int prec)
 {
     const bool wide = prec == FEM_FP64 || prec == FEM_FP32;

@@ -16,8 +16,8 @@ constexpr int MAX_VARIANTS = 7;
 // p = 2, 3 put 4 (8) and 2 (4) elements side by side; p = 4 gives one element to a workgroup
 // (variant 3: one element to each wave, 4 x 4 blocks in registers); p >= 5 tile one element
 // into row x column tiles (variant 2: 4 x 4 blocks per wave). FP64 uses 16-wide blocks. The
-// elasticity defaults p = 2, 3, 6 variant 6, p = 4 variant 4 and p = 5, 7 variant 5 are the
-// tiles (2, 1, 4, 3, 4, 4) whose epilogue also writes the transposed (lower) blocks.
+// elasticity defaults p = 2, 3, 6 variant 6, p = 4 variant 4 (FP32: 6) and p = 5, 7 variant 5
+// are the tiles (2, 1, 4, 3 (5), 4, 4) whose epilogue also writes the transposed (lower) blocks.
 template <int P, int FAM, int V> struct VariantCfg { using type = void; };
 // The vector-ALU kernel of trilinear hexahedra (fem_trilinear.h; ELEMENT mode only).
 struct TrilinearCfg {};
@@ -49,6 +49,7 @@ template <> struct VariantCfg<4, MF_K16, 2> { using type = Cfg<2, 1, 4, 4, 2, 2,
 template <> struct VariantCfg<4, MF_K16, 3> { using type = Cfg<4, 1, 4, 4, 4, 1, 1, 0, 1>; };
 template <> struct VariantCfg<4, MF_K16, 4> { using type = Cfg<4, 1, 4, 4, 4, 1, 1, 0, 1, 0, 1>; };
 template <> struct VariantCfg<4, MF_K16, 5> { using type = Cfg<2, 1, 4, 4, 2, 2, 1, 0, 1, 1>; };
+template <> struct VariantCfg<4, MF_K16, 6> { using type = Cfg<2, 1, 4, 4, 2, 2, 1, 0, 1, 1, 1>; };
 template <> struct VariantCfg<5, MF_K16, 0> { using type = Cfg<1, 1, 4, 4, 1, 1, 2, 0, 0>; };
 template <> struct VariantCfg<5, MF_K16, 1> { using type = Cfg<1, 1, 4, 4, 1, 1, 2, 0, 1>; };
 template <> struct VariantCfg<5, MF_K16, 2> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1>; };
@@ -353,6 +354,7 @@ constexpr int default_variant(int p, int fam, int mode)
     if (is_prism(p)) return 0;
     if (p == 1 && mode == 0) return trilinear_variant(p, fam);
     if (p == 4 && mode == 2 && fam == MF_K16) return 4;  // tile 3 that also writes transposed blocks
+    if (p == 4 && mode == 2 && fam == MF_F32) return 6;  // tile 5 that also writes transposed blocks
     if (mode == 2 && fam != MF_F64) {
         // the default tiles' twins that also write the transposed (lower) blocks
         if (p == 2 || p == 3 || p == 6) return 6;
