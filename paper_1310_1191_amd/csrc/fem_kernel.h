@@ -199,17 +199,17 @@ struct Shape {
                                       !(WAVE_OWNS_EL && C::NW == 1);
     static constexpr bool STAGE_WAVE = !STAGE_OUT && WAVE_OWNS_EL;
     // Tiles with TE can also write the transposed block (elasticity's lower blocks): with an odd
-    // Ns from a staged image (its column reads then free of bank conflicts), otherwise on the
-    // 32-wide families straight from the accumulators, whose four consecutive rows per lane make
-    // one run of a transposed row (16-byte stores where Ns is a multiple of 4). (Separate
-    // tiles, so the other instances carry none of this code.)
+    // Ns from a per-wave or whole-element staged image (its column reads then free of bank
+    // conflicts), otherwise on the 32-wide families straight from the accumulators, whose four
+    // consecutive rows per lane make one run of a transposed row (16-byte stores where Ns is a
+    // multiple of 4). (Separate tiles, so the other instances carry none of this code.)
     static constexpr bool TRANS_EPI = C::TE && (STAGE_WAVE || STAGE_OUT) && (NS % 2 == 1);
     static constexpr int WIMG = (TM * NS + 2 * VW - 1) / VW * VW;     // one row block
     // Otherwise a workgroup that owns whole elements with one row of waves stages one row block
     // of all its elements at a time.
     static constexpr bool STAGE_RB = !STAGE_OUT && !STAGE_WAVE && RT == 1 && CT == 1 && C::WGM == 1 &&
                                      size_t(EG) * WIMG * sizeof(OT) <= 65536;
-    static constexpr bool TRANS_REG = C::TE && FAM != MF_F64 && !STAGE_OUT && !TRANS_EPI;
+    static constexpr bool TRANS_REG = C::TE && FAM != MF_F64 && !TRANS_EPI;
     static constexpr size_t out_bytes = STAGE_OUT ? size_t(EG) * IMG * sizeof(OT)
                                       : STAGE_WAVE ? size_t(C::NW) * WIMG * sizeof(OT)
                                       : STAGE_RB ? size_t(EG) * WIMG * sizeof(OT) : 0;
@@ -1424,6 +1424,8 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
                         else img[row * NS + jj] = acc[i][j][v] * us;
                     }
                 }
+                if constexpr (S::TRANS_REG)
+                    if (trans) write_t(outA + a.at_base + e * a.a_stride, acc[i][j], (rb0 + i) * TM, jj, us);
             }
         }
         __syncthreads();

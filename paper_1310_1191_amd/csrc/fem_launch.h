@@ -73,21 +73,28 @@ template <> struct VariantCfg<7, MF_K16, 5> { using type = Cfg<1, 1, 4, 8, 2, 1,
 // column operand per wave from the B-factor table (PROD 1, BT 1). p = 1 packs 16 elements at a
 // pitch of 8 columns; p = 2, 3, 4 give one element to each wave (1 x 1, 2 x 2, 3 x 3 blocks);
 // p = 5 as the hexahedron of p = 4; p = 6 one element per workgroup in four 7 x 2 wave tiles;
-// p = 7 four tall 9 x 1 wave tiles (three column tiles) or three 9 x 1 waves.
+// p = 7 four tall 9 x 1 wave tiles (three column tiles) or three 9 x 1 waves. Variant 2 of
+// p >= 2 is variant 0 whose epilogue also writes the transposed elasticity blocks.
 template <> struct VariantCfg<11, MF_K16, 0> { using type = Cfg<16, 1, 1, 1, 4, 3, 1, 2, 1, 1>; };
 template <> struct VariantCfg<11, MF_K16, 1> { using type = Cfg<16, 1, 4, 1, 1, 3, 1, 2, 1, 1>; };
 template <> struct VariantCfg<12, MF_K16, 0> { using type = Cfg<4, 1, 1, 1, 4, 2, 1, 2, 1, 1>; };
 template <> struct VariantCfg<12, MF_K16, 1> { using type = Cfg<4, 1, 4, 1, 1, 3, 1, 2, 1, 1>; };
+template <> struct VariantCfg<12, MF_K16, 2> { using type = Cfg<4, 1, 1, 1, 4, 2, 1, 2, 1, 1, 1>; };
 template <> struct VariantCfg<13, MF_K16, 0> { using type = Cfg<4, 1, 4, 2, 2, 2, 1, 2, 1, 1>; };
 template <> struct VariantCfg<13, MF_K16, 1> { using type = Cfg<8, 1, 8, 2, 2, 2, 1, 1, 1, 1>; };
+template <> struct VariantCfg<13, MF_K16, 2> { using type = Cfg<4, 1, 4, 2, 2, 2, 1, 2, 1, 1, 1>; };
 template <> struct VariantCfg<14, MF_K16, 0> { using type = Cfg<4, 1, 4, 3, 3, 1, 1, 2, 1, 1>; };
 template <> struct VariantCfg<14, MF_K16, 1> { using type = Cfg<4, 1, 4, 3, 3, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<14, MF_K16, 2> { using type = Cfg<4, 1, 4, 3, 3, 1, 1, 2, 1, 1, 1>; };
 template <> struct VariantCfg<15, MF_K16, 0> { using type = Cfg<4, 1, 4, 4, 4, 1, 1, 0, 1, 1>; };
 template <> struct VariantCfg<15, MF_K16, 1> { using type = Cfg<1, 1, 4, 4, 1, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<15, MF_K16, 2> { using type = Cfg<4, 1, 4, 4, 4, 1, 1, 0, 1, 1, 1>; };
 template <> struct VariantCfg<16, MF_K16, 0> { using type = Cfg<1, 1, 4, 7, 2, 1, 1, 0, 1, 1>; };
 template <> struct VariantCfg<16, MF_K16, 1> { using type = Cfg<1, 1, 4, 7, 1, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<16, MF_K16, 2> { using type = Cfg<1, 1, 4, 7, 2, 1, 1, 0, 1, 1, 1>; };
 template <> struct VariantCfg<17, MF_K16, 0> { using type = Cfg<1, 1, 4, 9, 1, 1, 1, 0, 1, 1>; };
 template <> struct VariantCfg<17, MF_K16, 1> { using type = Cfg<1, 1, 3, 9, 1, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<17, MF_K16, 2> { using type = Cfg<1, 1, 4, 9, 1, 1, 1, 0, 1, 1, 1>; };
 template <int P, int V> struct VariantCfg<P, MF_F32, V> { using type = typename VariantCfg<P, MF_K16, V>::type; };
 // -- FP64 (16-wide blocks) --
 template <> struct VariantCfg<1, MF_F64, 0> { using type = Cfg<8, 1, 4, 1, 1, 2, 2, 1, 0>; };
@@ -351,7 +358,9 @@ int variants_p(int p)
 // p = 1 in ELEMENT mode (mode 0) runs the vector-ALU kernel.
 constexpr int default_variant(int p, int fam, int mode)
 {
-    if (is_prism(p)) return 0;
+    // prisms: tile 0; in ELASTIC mode on the 32-wide families its twin 2, which also writes the
+    // transposed (lower) blocks
+    if (is_prism(p)) return (mode == 2 && fam != MF_F64 && deg_of(p) >= 2) ? 2 : 0;
     if (p == 1 && mode == 0) return trilinear_variant(p, fam);
     if (p == 4 && mode == 2 && fam == MF_K16) return 4;  // tile 3 that also writes transposed blocks
     if (p == 4 && mode == 2 && fam == MF_F32) return 6;  // tile 5 that also writes transposed blocks

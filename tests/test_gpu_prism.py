@@ -84,6 +84,10 @@ def test_prism_elasticity_parity(fem, p, prec):
     eb = rel_vec(b.double().cpu().numpy().reshape(w.nel, -1), b_ref.reshape(w.nel, -1))
     log(f"[prism-elastic] p={p} prec={prec} errA max={ea.max():.3e} errb max={eb.max():.3e}")
     assert ea.max() <= TOL_A[prec] and eb.max() <= TOL_B[prec]
+    if p >= 2:  # lower blocks: transposes of the upper ones, from the epilogue or the copy kernel
+        for i in range(3):
+            for k in range(i + 1, 3):
+                assert torch.equal(A[:, k, i], A[:, i, k].transpose(1, 2)), (i, k)
 
 
 @pytest.mark.parametrize("p", [1, 3, 5, 7])
