@@ -32,6 +32,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstddef>
+
 #include <type_traits>
 
 #include "fem_geometry.h"
@@ -200,16 +202,17 @@ struct Shape {
     static constexpr bool STAGE_WAVE = !STAGE_OUT && WAVE_OWNS_EL;
     // Tiles with TE can also write the transposed block (elasticity's lower blocks): with an odd
     // Ns from a per-wave or whole-element staged image (its column reads then free of bank
-    // conflicts), otherwise on the 32-wide families straight from the accumulators, whose four
-    // consecutive rows per lane make one run of a transposed row (16-byte stores where Ns is a
-    // multiple of 4). (Separate tiles, so the other instances carry none of this code.)
+    // conflicts), otherwise straight from the accumulators (32-wide families: four consecutive
+    // rows per lane, one run of a transposed row, 16-byte stores where Ns is a multiple of 4;
+    // FP64: one value per row and four lanes per run). (Separate tiles, so the other instances
+    // carry none of this code.)
     static constexpr bool TRANS_EPI = C::TE && (STAGE_WAVE || STAGE_OUT) && (NS % 2 == 1);
     static constexpr int WIMG = (TM * NS + 2 * VW - 1) / VW * VW;     // one row block
     // Otherwise a workgroup that owns whole elements with one row of waves stages one row block
     // of all its elements at a time.
     static constexpr bool STAGE_RB = !STAGE_OUT && !STAGE_WAVE && RT == 1 && CT == 1 && C::WGM == 1 &&
                                      size_t(EG) * WIMG * sizeof(OT) <= 65536;
-    static constexpr bool TRANS_REG = C::TE && FAM != MF_F64 && !TRANS_EPI;
+    static constexpr bool TRANS_REG = C::TE && !TRANS_EPI;
     static constexpr size_t out_bytes = STAGE_OUT ? size_t(EG) * IMG * sizeof(OT)
                                       : STAGE_WAVE ? size_t(C::NW) * WIMG * sizeof(OT)
                                       : STAGE_RB ? size_t(EG) * WIMG * sizeof(OT) : 0;
@@ -1295,7 +1298,15 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
     // entries 4g .. 4g + 3 are four consecutive rows, so one 16-byte store each where the
     // destination is 16-byte aligned and all four rows exist, else scalar stores.
     auto write_t = [&](OT *dT, const typename F::acc &ac, int r0, int jj, float us) {
-        if constexpr (S::TRANS_REG) {
+        if constexpr (S::TRANS_REG && FAM == MF_F64) {
+            if (jj >= NS) return;
+            OT *rowp = dT + (int64_t)jj * NS;
+#pragma unroll
+            for (int v = 0; v < F::ACC_N; ++v) {
+                const int row = r0 + acc_row<FAM>(lane, v);
+                if (row < NS) rowp[row] = ac[v];
+            }
+        } else if constexpr (S::TRANS_REG) {
             static_assert(std::is_same<OT, float>::value, "the 32-wide families write FP32");
             if (jj >= NS) return;
             OT *rowp = dT + (int64_t)jj * NS;
@@ -1585,6 +1596,11 @@ struct MixedKArgs {
     KArgs deg[7];     // deg[p - 1]: the bucket of degree p (seg = its {start, count})
     int32_t tile[8];  // tile[p - 1]: the tile alternative (0, 1) degree p runs with
 };
+// mixed_args reads deg[d] from the kernel-argument segment, where the launch's only argument
+// starts at offset 0: a plain copyable struct whose first member is deg
+static_assert(std::is_trivially_copyable<MixedKArgs>::value && std::is_standard_layout<MixedKArgs>::value &&
+                  offsetof(MixedKArgs, deg) == 0,
+              "MixedKArgs is read through the argument segment");
 
 // The arguments of degree d + 1, read from the kernel-argument segment (the launch's only
 // argument, a MixedKArgs, starts at its offset 0) through a pointer the compiler cannot see

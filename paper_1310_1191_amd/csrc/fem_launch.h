@@ -17,7 +17,9 @@ constexpr int MAX_VARIANTS = 7;
 // (variant 3: one element to each wave, 4 x 4 blocks in registers); p >= 5 tile one element
 // into row x column tiles (variant 2: 4 x 4 blocks per wave). FP64 uses 16-wide blocks. The
 // elasticity defaults p = 2, 3, 6 variant 6, p = 4 variant 4 (FP32: 6) and p = 5, 7 variant 5
-// are the tiles (2, 1, 4, 3 (5), 4, 4) whose epilogue also writes the transposed (lower) blocks.
+// are the tiles (2, 1, 4, 3 (5), 4, 4) whose epilogue also writes the transposed (lower) blocks;
+// the last FP64 variant of p >= 2 (and variant 1 of the FP64 prisms) is the same twin of the
+// FP64 default.
 template <int P, int FAM, int V> struct VariantCfg { using type = void; };
 // The vector-ALU kernel of trilinear hexahedra (fem_trilinear.h; ELEMENT mode only).
 struct TrilinearCfg {};
@@ -102,27 +104,39 @@ template <> struct VariantCfg<1, MF_F64, 1> { using type = TrilinearCfg; };
 template <> struct VariantCfg<2, MF_F64, 0> { using type = Cfg<2, 1, 4, 2, 1, 2, 2, 0, 0>; };
 template <> struct VariantCfg<2, MF_F64, 1> { using type = Cfg<4, 1, 4, 2, 2, 2, 1, 2, 1, 1>; };
 template <> struct VariantCfg<2, MF_F64, 2> { using type = Cfg<4, 1, 1, 2, 8, 2, 1, 2, 1, 1>; };
+template <> struct VariantCfg<2, MF_F64, 3> { using type = Cfg<4, 1, 4, 2, 2, 2, 1, 2, 1, 1, 1>; };
 template <> struct VariantCfg<3, MF_F64, 0> { using type = Cfg<1, 1, 4, 4, 1, 2, 2, 0, 0>; };
 template <> struct VariantCfg<3, MF_F64, 1> { using type = Cfg<2, 1, 4, 4, 2, 2, 1, 2, 1, 1>; };
 template <> struct VariantCfg<3, MF_F64, 2> { using type = Cfg<1, 1, 4, 4, 1, 2, 1, 2, 1, 1>; };
+template <> struct VariantCfg<3, MF_F64, 3> { using type = Cfg<2, 1, 4, 4, 2, 2, 1, 2, 1, 1, 1>; };
 template <> struct VariantCfg<4, MF_F64, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 1, 0, 0>; };
 template <> struct VariantCfg<4, MF_F64, 1> { using type = Cfg<1, 1, 4, 8, 2, 1, 1, 0, 1>; };
 template <> struct VariantCfg<4, MF_F64, 2> { using type = Cfg<1, 1, 4, 8, 2, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<4, MF_F64, 3> { using type = Cfg<1, 1, 4, 8, 2, 1, 1, 0, 1, 0, 1>; };
 template <> struct VariantCfg<5, MF_F64, 0> { using type = Cfg<1, 1, 4, 7, 1, 1, 1, 0, 0>; };
 template <> struct VariantCfg<5, MF_F64, 1> { using type = Cfg<1, 1, 4, 14, 1, 1, 1, 0, 0>; };
+template <> struct VariantCfg<5, MF_F64, 2> { using type = Cfg<1, 1, 4, 14, 1, 1, 1, 0, 0, 0, 1>; };
 template <> struct VariantCfg<6, MF_F64, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 1, 0, 0>; };
 template <> struct VariantCfg<6, MF_F64, 1> { using type = Cfg<1, 1, 4, 11, 1, 1, 1, 0, 0>; };
+template <> struct VariantCfg<6, MF_F64, 2> { using type = Cfg<1, 1, 4, 11, 1, 1, 1, 0, 0, 0, 1>; };
 template <> struct VariantCfg<7, MF_F64, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 1, 0, 0>; };
 template <> struct VariantCfg<7, MF_F64, 1> { using type = Cfg<1, 1, 4, 16, 1, 1, 1, 0, 0>; };
+template <> struct VariantCfg<7, MF_F64, 2> { using type = Cfg<1, 1, 4, 16, 1, 1, 1, 0, 0, 0, 1>; };
 // prisms, 16-wide blocks: p = 1 packs 8 elements per wave; p = 2, 3 one element per wave; p >= 4
 // one element per workgroup in tall wave tiles holding every row block
 template <> struct VariantCfg<11, MF_F64, 0> { using type = Cfg<8, 1, 1, 1, 4, 2, 1, 2, 1, 1>; };
 template <> struct VariantCfg<12, MF_F64, 0> { using type = Cfg<4, 1, 4, 2, 2, 2, 1, 2, 1, 1>; };
+template <> struct VariantCfg<12, MF_F64, 1> { using type = Cfg<4, 1, 4, 2, 2, 2, 1, 2, 1, 1, 1>; };
 template <> struct VariantCfg<13, MF_F64, 0> { using type = Cfg<4, 1, 4, 3, 3, 1, 1, 2, 1, 1>; };
+template <> struct VariantCfg<13, MF_F64, 1> { using type = Cfg<4, 1, 4, 3, 3, 1, 1, 2, 1, 1, 1>; };
 template <> struct VariantCfg<14, MF_F64, 0> { using type = Cfg<1, 1, 4, 5, 1, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<14, MF_F64, 1> { using type = Cfg<1, 1, 4, 5, 1, 1, 1, 0, 1, 1, 1>; };
 template <> struct VariantCfg<15, MF_F64, 0> { using type = Cfg<1, 1, 4, 8, 1, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<15, MF_F64, 1> { using type = Cfg<1, 1, 4, 8, 1, 1, 1, 0, 1, 1, 1>; };
 template <> struct VariantCfg<16, MF_F64, 0> { using type = Cfg<1, 1, 4, 13, 1, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<16, MF_F64, 1> { using type = Cfg<1, 1, 4, 13, 1, 1, 1, 0, 1, 1, 1>; };
 template <> struct VariantCfg<17, MF_F64, 0> { using type = Cfg<1, 1, 4, 18, 1, 1, 1, 0, 1, 1>; };
+template <> struct VariantCfg<17, MF_F64, 1> { using type = Cfg<1, 1, 4, 18, 1, 1, 1, 0, 1, 1, 1>; };
 
 template <int P, int PREC, int V>
 struct Inst {
@@ -358,12 +372,13 @@ int variants_p(int p)
 // p = 1 in ELEMENT mode (mode 0) runs the vector-ALU kernel.
 constexpr int default_variant(int p, int fam, int mode)
 {
-    // prisms: tile 0; in ELASTIC mode on the 32-wide families its twin 2, which also writes the
-    // transposed (lower) blocks
-    if (is_prism(p)) return (mode == 2 && fam != MF_F64 && deg_of(p) >= 2) ? 2 : 0;
+    // prisms: tile 0; in ELASTIC mode its twin (2, FP64: 1), which also writes the transposed
+    // (lower) blocks
+    if (is_prism(p)) return (mode == 2 && deg_of(p) >= 2) ? (fam == MF_F64 ? 1 : 2) : 0;
     if (p == 1 && mode == 0) return trilinear_variant(p, fam);
     if (p == 4 && mode == 2 && fam == MF_K16) return 4;  // tile 3 that also writes transposed blocks
     if (p == 4 && mode == 2 && fam == MF_F32) return 6;  // tile 5 that also writes transposed blocks
+    if (mode == 2 && fam == MF_F64 && p >= 2) return p <= 4 ? 3 : 2;  // FP64 twins (below)
     if (mode == 2 && fam != MF_F64) {
         // the default tiles' twins that also write the transposed (lower) blocks
         if (p == 2 || p == 3 || p == 6) return 6;

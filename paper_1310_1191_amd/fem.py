@@ -588,6 +588,8 @@ def gather_sample(sel, a_off, A, out_A, precision, b_off=None, b=None, out_b=Non
         _check(b, dt, "b")
         _check(out_b, dt, "out_b")
         _check(b_off, torch.int64, "b_off", shape=tuple(a_off.shape))
+    if sel.dim() not in (1, 2):
+        raise ValueError("sel: [nsel] or [nrows, nsel] element ids")
     nrows, nsel = (1, sel.shape[0]) if sel.dim() == 1 else (sel.shape[0], sel.shape[1])
     rc = fem_gather_sample(nsel, _ptr(sel), nrows, _ptr(step) if step is not None else None,
                            a_off.shape[0] - 1, _ptr(a_off), _ptr(b_off) if b_off is not None else None,

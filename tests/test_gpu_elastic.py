@@ -101,14 +101,16 @@ def test_elastic_blocks_are_transposes(fem, p, prec):
             assert err.max() <= TOL_A[prec], (i, k, err.max())
 
 
-@pytest.mark.parametrize("p,prec", [(4, "split_fp16"), (4, "bf16"), (4, "fp32"), (2, "split_fp16"), (2, "fp32"),
-                                    (2, "fp64"), (3, "split_fp16"), (3, "fp32"), (5, "split_fp16"),
-                                    (5, "fp32"), (6, "split_fp16"), (7, "split_fp16"), (7, "fp32")])
+@pytest.mark.parametrize("p,prec", [(4, "split_fp16"), (4, "bf16"), (4, "fp32"), (4, "fp64"), (2, "split_fp16"),
+                                    (2, "fp32"), (2, "fp64"), (3, "split_fp16"), (3, "fp32"), (3, "fp64"),
+                                    (5, "split_fp16"), (5, "fp32"), (5, "fp64"), (6, "split_fp16"),
+                                    (7, "split_fp16"), (7, "fp32"), (7, "fp64")])
 def test_lower_blocks_every_tile(fem, p, prec):
     """The default ELASTIC tile writes the lower blocks transposed from its epilogue: from the
     staged image (per wave at p = 4, whole elements at p = 2) or straight from the accumulators
-    (p = 3, 5, 6, 7, and p = 4 in FP32); every other tile (which cannot), and FP64, falls back to the copy kernel. All
-    give the oracle's blocks, and the lower blocks equal the transposed upper ones bit for bit."""
+    (the other degrees, FP32 p = 4, FP64 p >= 3); every other tile (which cannot) falls back to
+    the copy kernel. All give the oracle's blocks, and the lower blocks equal the transposed upper
+    ones bit for bit."""
     import torch
     geom, coef, A_ref, _, _ = elastic_case(p)
     # a ragged last element group where the mesh has several elements (p = 2: 4 per group)
