@@ -125,9 +125,11 @@ def test_supplied_terms_elasticity(fem, p):
         assert ea.max() <= TOL_A[prec] and eb.max() <= TOL_B[prec]
 
 
-@pytest.mark.parametrize("strategy", [0, 1])
+@pytest.mark.parametrize("case", ["single", "single_other_tiles", "per_degree"])
 @pytest.mark.parametrize("prec", ["fp64", "split_fp16"])
-def test_supplied_terms_mixed_degree(fem, prec, strategy):
+def test_supplied_terms_mixed_degree(fem, prec, case):
+    """Supplied terms through the mixed-degree path: the single launch with its default tiles or
+    with the other tile of every degree (its supplied-terms instance), and per-degree launches."""
     import oracle
     import torch
     w = synth.make(4, grid=(7, 5, 4))
@@ -137,21 +139,29 @@ def test_supplied_terms_mixed_degree(fem, prec, strategy):
     a_off, b_off = fem.mixed_offsets(d)
     jt = fem.jacobian_terms(g, 0, degree=d, b_off=b_off)
     code = fem.PRECISIONS[prec]
-    saved = fem.fem_get_variant(0, code, fem.FIELD)
+    keys = [0] + [fem.mixed(p) for p in range(1, 8)]
+    saved = {k: fem.fem_get_variant(k, code, fem.FIELD) for k in keys}
+    strategy = 1 if case == "per_degree" else 0
     fem.fem_set_variant(0, code, fem.FIELD, strategy)
+    if case == "single_other_tiles":
+        for p in range(1, 8):
+            n = fem.fem_variant_count(fem.mixed(p), code)
+            fem.fem_set_variant(fem.mixed(p), code, fem.FIELD, n - 1)
     try:
+        print(f"[nojac-mixed] prec={prec} case={case}", flush=True)
         A, b, _, _ = fem.integrate_mixed(g, c, d, precision=prec, mode=fem.FIELD, field=f,
                                          a_off=a_off, b_off=b_off, jac=jt)
         torch.cuda.synchronize()
     finally:
-        fem.fem_set_variant(0, code, fem.FIELD, saved)
+        for k, v in saved.items():
+            fem.fem_set_variant(k, code, fem.FIELD, v)
     A = A.double().cpu().numpy()
     b = b.double().cpu().numpy()
     ea = max(rel_fro(A[a_ref[e]:a_ref[e + 1]].reshape(1, -1, 1),
                      A_ref[a_ref[e]:a_ref[e + 1]].reshape(1, -1, 1))[0] for e in range(w.nel))
     eb = max(rel_vec(b[None, b_ref_off[e]:b_ref_off[e + 1]],
                      b_ref[None, b_ref_off[e]:b_ref_off[e + 1]])[0] for e in range(w.nel))
-    log(f"[nojac] mixed prec={prec} strategy={strategy} errA max={ea:.3e} errb max={eb:.3e}")
+    log(f"[nojac] mixed prec={prec} case={case} errA max={ea:.3e} errb max={eb:.3e}")
     assert ea <= TOL_A[prec] and eb <= TOL_B[prec]
 
 
