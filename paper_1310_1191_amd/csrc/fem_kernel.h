@@ -86,7 +86,7 @@ struct KArgs {
 };
 
 template <int EG_, int WGM_, int WGN_, int WM_, int WN_, int OCC_, int KC_, int RES_, int PROD_ = 0,
-          int BT_ = 0, int TE_ = 0>
+          int BT_ = 0, int TE_ = 0, int OPQ_ = 0>
 struct Cfg {
     static constexpr int PROD = PROD_;  // 0: C chunks produced by the whole workgroup into LDS;
                                         // 1: each wave produces its own C fragments in registers
@@ -105,9 +105,10 @@ struct Cfg {
     static constexpr int BT = BT_;    // PROD 1 only: 1 reads the B factors of the column operand
                                       // from a precomputed table instead of forming them from the
                                       // 1-D Lagrange tables
-    static constexpr int TE = TE_;    // 1: the per-wave or whole-element staged epilogue can also
-                                      // write the block transposed (elasticity's lower blocks,
-                                      // KArgs::at_base), where Ns is odd
+    static constexpr int TE = TE_;    // 1: the epilogue can also write the block transposed
+                                      // (elasticity's lower blocks, KArgs::at_base)
+    static constexpr int OPQ = OPQ_;  // 1: the per-thread addresses are formed again in every
+                                      // item instead of being kept across the item loop
     static constexpr int NW = WGM_ * WGN_;
 };
 
@@ -636,7 +637,12 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
     unsigned char *s_rb0 = smem + S::off_cb + S::NBUF * S::CBUF;
     unsigned char *s_rb1 = s_rb0 + S::RBUF;
 
-    const int tid = threadIdx.x;
+    // OPQ tiles pass the thread index through an empty asm statement once per item, so the
+    // per-thread addresses derived from it are formed again in each item instead of being kept
+    // across the item loop: where that loop spilled them, their reloads at the top of the next
+    // item waited, in the in-order vector-memory counter, for all of this item's output stores.
+    int tid = threadIdx.x;
+    if constexpr (C::OPQ) asm volatile("" : "+v"(tid));
     const int neg = it.neg, rt = it.rt, ct = it.ct;
     const int64_t e0 = it.e0;
 

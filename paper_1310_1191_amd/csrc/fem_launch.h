@@ -9,7 +9,7 @@ namespace fem {
 
 constexpr int MAX_VARIANTS = 7;
 
-// Cfg<EG, WGM, WGN, WM, WN, OCC, KC, RES, PROD> (see fem_kernel.h). For the 32-wide families
+// Cfg<EG, WGM, WGN, WM, WN, OCC, KC, RES, PROD, BT, TE, OPQ> (see fem_kernel.h). For the 32-wide families
 // (FP32, BF16, split): p = 1 packs 16 elements of 8 trial functions into 4 column blocks
 // (variants 3, 4: the two k-groups of row fragments held in registers; variant 5 the
 // vector-ALU kernel of fem_trilinear.h, ELEMENT mode only);
@@ -56,8 +56,8 @@ template <> struct VariantCfg<5, MF_K16, 0> { using type = Cfg<1, 1, 4, 4, 1, 1,
 template <> struct VariantCfg<5, MF_K16, 1> { using type = Cfg<1, 1, 4, 4, 1, 1, 2, 0, 1>; };
 template <> struct VariantCfg<5, MF_K16, 2> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1>; };
 template <> struct VariantCfg<5, MF_K16, 3> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1, 1>; };
-template <> struct VariantCfg<5, MF_K16, 4> { using type = Cfg<1, 1, 4, 7, 2, 1, 1, 0, 1>; };
-template <> struct VariantCfg<5, MF_K16, 5> { using type = Cfg<1, 1, 4, 7, 2, 1, 1, 0, 1, 0, 1>; };
+template <> struct VariantCfg<5, MF_K16, 4> { using type = Cfg<1, 1, 4, 7, 2, 1, 1, 0, 1, 0, 0, 1>; };
+template <> struct VariantCfg<5, MF_K16, 5> { using type = Cfg<1, 1, 4, 7, 2, 1, 1, 0, 1, 0, 1, 1>; };
 template <> struct VariantCfg<6, MF_K16, 0> { using type = Cfg<1, 1, 4, 6, 1, 1, 2, 0, 0>; };
 template <> struct VariantCfg<6, MF_K16, 1> { using type = Cfg<1, 1, 4, 6, 1, 1, 2, 0, 1>; };
 template <> struct VariantCfg<6, MF_K16, 2> { using type = Cfg<1, 3, 1, 4, 4, 1, 1, 0, 1>; };
@@ -69,8 +69,8 @@ template <> struct VariantCfg<7, MF_K16, 0> { using type = Cfg<1, 1, 4, 8, 1, 1,
 template <> struct VariantCfg<7, MF_K16, 1> { using type = Cfg<1, 1, 4, 8, 1, 1, 2, 0, 1>; };
 template <> struct VariantCfg<7, MF_K16, 2> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1>; };
 template <> struct VariantCfg<7, MF_K16, 3> { using type = Cfg<1, 2, 2, 4, 4, 1, 1, 0, 1, 1>; };
-template <> struct VariantCfg<7, MF_K16, 4> { using type = Cfg<1, 1, 4, 8, 2, 1, 1, 0, 1>; };
-template <> struct VariantCfg<7, MF_K16, 5> { using type = Cfg<1, 1, 4, 8, 2, 1, 1, 0, 1, 0, 1>; };
+template <> struct VariantCfg<7, MF_K16, 4> { using type = Cfg<1, 1, 4, 8, 2, 1, 1, 0, 1, 0, 0, 1>; };
+template <> struct VariantCfg<7, MF_K16, 5> { using type = Cfg<1, 1, 4, 8, 2, 1, 1, 0, 1, 0, 1, 1>; };
 // -- prisms (P = PRISM_BASE + p; Ns = 6, 18, 40, 75, 126, 196, 288): every variant produces the
 // column operand per wave from the B-factor table (PROD 1, BT 1). p = 1 packs 16 elements at a
 // pitch of 8 columns; p = 2, 3, 4 give one element to each wave (1 x 1, 2 x 2, 3 x 3 blocks);
