@@ -372,9 +372,17 @@ int variants_p(int p)
 // p = 1 in ELEMENT mode (mode 0) runs the vector-ALU kernel.
 constexpr int default_variant(int p, int fam, int mode)
 {
-    // prisms: tile 0; in ELASTIC mode its twin (2, FP64: 1), which also writes the transposed
-    // (lower) blocks
-    if (is_prism(p)) return (mode == 2 && deg_of(p) >= 2) ? (fam == MF_F64 ? 1 : 2) : 0;
+    // prisms: the fastest measured per (family, degree, mode) on MI355X at the prism workload
+    // sizes (fem_autotune over every variant); variant 2 (FP64: 1) is tile 0 that also writes
+    // the transposed elasticity blocks
+    if (is_prism(p)) {
+        const int d = deg_of(p);
+        constexpr int k16[2][8] = {{0, 1, 2, 2, 2, 2, 0, 1}, {0, 1, 2, 2, 2, 2, 2, 1}};
+        constexpr int f32[2][8] = {{0, 1, 2, 1, 1, 2, 0, 0}, {0, 1, 2, 2, 1, 2, 2, 2}};
+        constexpr int f64[2][8] = {{0, 0, 1, 1, 1, 0, 1, 0}, {0, 0, 1, 1, 1, 1, 1, 0}};
+        const int m = mode == 2 ? 1 : 0;
+        return fam == MF_F64 ? f64[m][d] : (fam == MF_F32 ? f32[m][d] : k16[m][d]);
+    }
     if (p == 1 && mode == 0) return trilinear_variant(p, fam);
     if (p == 4 && mode == 2 && fam == MF_K16) return 4;  // tile 3 that also writes transposed blocks
     if (p == 4 && mode == 2 && fam == MF_F32) return 6;  // tile 5 that also writes transposed blocks
