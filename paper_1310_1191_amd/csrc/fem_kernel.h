@@ -647,24 +647,30 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
     const int64_t e0 = it.e0;
 
     // ---- element data (fetched earlier) into LDS ----
+    // The item's first phases take the thread index through an empty asm statement: their
+    // addresses are formed again here instead of being held across the item loop, where the
+    // compiler spilled them and the reloads at the top of the item waited for the previous
+    // item's stores (the vector-memory counter is in order).
+    int tid_top = threadIdx.x;
+    asm volatile("" : "+v"(tid_top));
 #pragma unroll
     for (int k = 0; k < S::PFN; ++k) {
-        const int f = tid + k * NT;
+        const int f = tid_top + k * NT;
         const int el = f / S::EREC, comp = f % S::EREC;
         if (el < EG) {
             if (comp < 24) s_geo[el * 24 + comp] = pf[k];
             else s_rec[el * 14 + (comp - 24)] = pf[k];
         }
     }
-    if (tid < EG) {
-        s_dmax[tid] = 0u;
-        s_flag[tid] = 0;
+    if (tid_top < EG) {
+        s_dmax[tid_top] = 0u;
+        s_flag[tid_top] = 0;
     }
     __syncthreads();
 
     // ---- trilinear form x(xi) = sum_S c_S prod_{d in S} xi_d, c_S = 1/8 sum_v X_v prod s_vd ----
     if constexpr (!S::PRISM) {
-        for (int t = tid; t < EG * 24; t += NT) {
+        for (int t = tid_top; t < EG * 24; t += NT) {
             const int el = t / 24, coord = (t % 24) / 8, sub = t % 8;
             s_tc[t] = trilinear_coeff(s_geo + el * 24, coord, sub);
         }
