@@ -1159,6 +1159,10 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
         }
     };
 
+    // Tiles with two or more waves per SIMD raise the wave's issue priority for the main loop, so
+    // that its matrix-core instructions go ahead of another wave's prologue or epilogue work on
+    // the same SIMD; the priority drops back before the load vector.
+    if constexpr (C::OCC > 1) __builtin_amdgcn_s_setprio(2);
     if constexpr (C::RES == 3) {
         // ---- main loop, rows held in registers: the wave's row fragments of every k-group are
         // loaded at once (one L2 round trip per item), the k loop is unrolled, no barrier.
@@ -1211,6 +1215,7 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
         consume_chunk(S::NCH - 1, ((S::NCH - 1) & 1) ? s_cb1 : s_cb0, ((S::NCH - 1) & 1) ? s_rb1 : s_rb0);
     }
 
+    if constexpr (C::OCC > 1) __builtin_amdgcn_s_setprio(0);
     using OT = typename S::OT;
     __syncthreads();  // every wave is done with the point matrices and the chunks
 
