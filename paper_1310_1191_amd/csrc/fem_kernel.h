@@ -647,6 +647,7 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
     const int64_t e0 = it.e0;
 
     // ---- element data (fetched earlier) into LDS ----
+    if constexpr (C::OCC > 1) __builtin_amdgcn_s_setprio(0);  // prologue: lowest
     // The item's first phases take the thread index through an empty asm statement: their
     // addresses are formed again here instead of being held across the item loop, where the
     // compiler spilled them and the reloads at the top of the item waited for the previous
@@ -1159,9 +1160,9 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
         }
     };
 
-    // Tiles with two or more waves per SIMD raise the wave's issue priority for the main loop, so
-    // that its matrix-core instructions go ahead of another wave's prologue or epilogue work on
-    // the same SIMD; the priority drops back before the load vector.
+    // Tiles with two or more waves per SIMD order their waves' issue by phase: the main loop
+    // (matrix-core work) first, then the load vector and the stores, then the prologue, so
+    // that the waves on one SIMD overlap one another's phases instead of contending.
     if constexpr (C::OCC > 1) __builtin_amdgcn_s_setprio(2);
     if constexpr (C::RES == 3) {
         // ---- main loop, rows held in registers: the wave's row fragments of every k-group are
@@ -1215,7 +1216,7 @@ __device__ inline void integrate_item(const KArgs &a, const Item &it, const int3
         consume_chunk(S::NCH - 1, ((S::NCH - 1) & 1) ? s_cb1 : s_cb0, ((S::NCH - 1) & 1) ? s_rb1 : s_rb0);
     }
 
-    if constexpr (C::OCC > 1) __builtin_amdgcn_s_setprio(0);
+    if constexpr (C::OCC > 1) __builtin_amdgcn_s_setprio(1);
     using OT = typename S::OT;
     __syncthreads();  // every wave is done with the point matrices and the chunks
 
